@@ -1,0 +1,319 @@
+"""Pins of the CPU oracle against facts outside the oracle itself.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped or
+doubled term, a wrong sign in the complex product, a transposed operand, a
+wrong leading dimension, reading B_old when beta == 0) fails at least one test:
+
+* exact integer brute force (numpy int64 matmul is exact; binary64 sums of
+  small integer products are exact as long as they stay below 2^53);
+* exact rational results (Python ``fractions``) with the classical error bound
+  of a recursive dot product, |fl(x.y) - x.y| <= gamma_n sum |x_i y_i|, and the
+  Dot2 bound u|x.y| + gamma_n^2 sum |x_i y_i| (Ogita, Rump, Oishi 2005);
+* closed forms (all-ones, identity, unit matrices, K = 0);
+* invariants (A^T A symmetric, C(A,B) = C(B,A)^T, power-of-two linearity,
+  complex = real expansion, TSMM row by row);
+* the library routine numpy BLAS ``A.T @ B`` / ``A @ C`` (Section 1.5 notes the
+  products are plain GEMMs on transposed column-major views).
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1905_03136_amd import inputs
+
+U = 2.0 ** -53
+
+
+def gamma(n):
+    return n * U / (1 - n * U)
+
+
+def exact_int_tsmttsm(A, B, conj=False):
+    """Exact A^T B of integer-valued matrices with int64 arithmetic."""
+    if np.iscomplexobj(A):
+        Ar, Ai = A.real.astype(np.int64), A.imag.astype(np.int64)
+        Br, Bi = B.real.astype(np.int64), B.imag.astype(np.int64)
+        if conj:
+            Ai = -Ai
+        return (Ar.T @ Br - Ai.T @ Bi).astype(np.float64) + 1j * (Ar.T @ Bi + Ai.T @ Br).astype(np.float64)
+    return (A.astype(np.int64).T @ B.astype(np.int64)).astype(np.float64)
+
+
+def exact_int_tsmm(A, C, conj=False):
+    if np.iscomplexobj(A):
+        Ar, Ai = A.real.astype(np.int64), A.imag.astype(np.int64)
+        Cr, Ci = C.real.astype(np.int64), C.imag.astype(np.int64)
+        if conj:
+            Ai = -Ai
+        return (Ar @ Cr - Ai @ Ci).astype(np.float64) + 1j * (Ar @ Ci + Ai @ Cr).astype(np.float64)
+    return (A.astype(np.int64) @ C.astype(np.int64)).astype(np.float64)
+
+
+SHAPES = [(1, 1), (2, 3), (3, 2), (5, 7), (8, 8), (16, 4), (4, 16), (13, 1), (1, 13)]
+
+
+# ------------------------------------------------------------ exact integers
+@pytest.mark.parametrize("M,N", SHAPES)
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tsmttsm_exact_integers(oracle_mod, M, N, cplx):
+    K = 1000
+    A = inputs.host_integers(K, M, 1, inputs.STREAM_A, cplx)
+    B = inputs.host_integers(K, N, 1, inputs.STREAM_B, cplx)
+    for comp in (False, True):
+        C = oracle_mod.tsmttsm(A, B, compensated=comp)
+        assert np.array_equal(C, exact_int_tsmttsm(A, B))
+    if cplx:
+        C = oracle_mod.tsmttsm(A, B, op="C")
+        assert np.array_equal(C, exact_int_tsmttsm(A, B, conj=True))
+
+
+@pytest.mark.parametrize("M,N", SHAPES)
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tsmm_exact_integers(oracle_mod, M, N, cplx):
+    K = 777
+    A = inputs.host_integers(K, M, 2, inputs.STREAM_A, cplx)
+    C = inputs.host_integers(M, N, 2, inputs.STREAM_C, cplx)
+    B0 = inputs.host_integers(K, N, 2, inputs.STREAM_B, cplx)
+    P = exact_int_tsmm(A, C)
+    assert np.array_equal(oracle_mod.tsmm(A, C), P)
+    assert np.array_equal(oracle_mod.tsmm(A, C, compensated=True), P)
+    assert np.array_equal(oracle_mod.tsmm(A, C, alpha=-2.0), -2 * P)
+    # alpha and beta powers of two / small integers keep everything exact
+    B = oracle_mod.tsmm(A, C, B0.copy(), alpha=2.0, beta=-3.0)
+    assert np.array_equal(B, 2 * P - 3 * B0)
+    B = oracle_mod.tsmm(A, C, B0.copy(), alpha=-1.0, beta=1.0)
+    assert np.array_equal(B, B0 - P)
+    if cplx:
+        assert np.array_equal(oracle_mod.tsmm(A, C, conjA=True), exact_int_tsmm(A, C, conj=True))
+
+
+# --------------------------------------------- exact rationals + error bound
+def _frac_dot_real(x, y):
+    return sum((Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y)), Fraction(0))
+
+
+def _frac_dot_cplx(x, y, conj=False):
+    re = Fraction(0)
+    im = Fraction(0)
+    for a, b in zip(x, y):
+        ar, ai = Fraction(float(a.real)), Fraction(float(a.imag))
+        if conj:
+            ai = -ai
+        br, bi = Fraction(float(b.real)), Fraction(float(b.imag))
+        re += ar * br - ai * bi
+        im += ar * bi + ai * br
+    return re, im
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tsmttsm_error_bounds_vs_exact(oracle_mod, cplx):
+    K, M, N = 200, 3, 4
+    A = inputs.host_uniform(K, M, 3, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, N, 3, inputs.STREAM_B, cplx)
+    for op in (("T", "C") if cplx else ("T",)):
+        Cp = oracle_mod.tsmttsm(A, B, op=op)
+        Cc = oracle_mod.tsmttsm(A, B, op=op, compensated=True)
+        for m in range(M):
+            for n in range(N):
+                x, y = A[:, m], B[:, n]
+                if not cplx:
+                    ex = _frac_dot_real(x, y)
+                    absum = float(np.sum(np.abs(x * y)))
+                    assert abs(Fraction(Cp[m, n]) - ex) <= Fraction(gamma(K) * absum)
+                    assert abs(Fraction(Cc[m, n]) - ex) <= Fraction(U * abs(float(ex)) + gamma(K) ** 2 * absum)
+                else:
+                    er, ei = _frac_dot_cplx(x, y, conj=(op == "C"))
+                    sr = float(np.sum(np.abs(x.real * y.real)) + np.sum(np.abs(x.imag * y.imag)))
+                    si = float(np.sum(np.abs(x.real * y.imag)) + np.sum(np.abs(x.imag * y.real)))
+                    # each term is a 2-product expression: K+1 roundings bound the recursive sum
+                    assert abs(Fraction(Cp[m, n].real) - er) <= Fraction(gamma(K + 1) * sr)
+                    assert abs(Fraction(Cp[m, n].imag) - ei) <= Fraction(gamma(K + 1) * si)
+                    assert abs(Fraction(Cc[m, n].real) - er) <= Fraction(U * abs(float(er)) + gamma(2 * K) ** 2 * sr)
+                    assert abs(Fraction(Cc[m, n].imag) - ei) <= Fraction(U * abs(float(ei)) + gamma(2 * K) ** 2 * si)
+
+
+def test_compensated_beats_plain_on_cancelling_sum(oracle_mod):
+    # a dot product with heavy cancellation: x = (big, 1, -big), y = 1
+    K = 3000
+    x = inputs.host_uniform(K, 1, 4, inputs.STREAM_A)
+    x[::2] *= 1e8
+    y = np.ones((K, 1))
+    y[1::2] = 1.0
+    x[-1, 0] = -float(np.sum([Fraction(v) for v in x[:-1, 0]]))  # nearly cancel the total
+    ex = _frac_dot_real(x[:, 0], y[:, 0])
+    cp = oracle_mod.tsmttsm(x, y)[0, 0]
+    cc = oracle_mod.tsmttsm(x, y, compensated=True)[0, 0]
+    err_c = abs(Fraction(cc) - ex)
+    assert err_c <= Fraction(U * abs(float(ex)) + gamma(K) ** 2 * float(np.sum(np.abs(x))))
+    assert err_c <= abs(Fraction(cp) - ex)
+
+
+def test_tsmm_error_bound_vs_exact(oracle_mod):
+    K, M, N = 40, 7, 5
+    A = inputs.host_uniform(K, M, 5, inputs.STREAM_A)
+    C = inputs.host_uniform(M, N, 5, inputs.STREAM_C)
+    B = oracle_mod.tsmm(A, C)
+    for k in range(K):
+        for n in range(N):
+            ex = _frac_dot_real(A[k], C[:, n])
+            absum = float(np.sum(np.abs(A[k] * C[:, n])))
+            assert abs(Fraction(B[k, n]) - ex) <= Fraction(gamma(M) * absum)
+
+
+# ------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("cplx", [False, True])
+def test_closed_forms(oracle_mod, cplx):
+    dt = np.complex128 if cplx else np.float64
+    K, M, N = 4099, 6, 5
+    C = oracle_mod.tsmttsm(np.ones((K, M), dt), np.ones((K, N), dt))
+    assert np.array_equal(C, np.full((M, N), float(K), dt))
+    # A = identity (K = M): C = first M rows of B
+    B = inputs.host_uniform(M, N, 6, inputs.STREAM_B, cplx)
+    assert np.array_equal(oracle_mod.tsmttsm(np.eye(M, dtype=dt), B), B)
+    # TSMM with C = identity returns A exactly
+    A = inputs.host_uniform(K, M, 6, inputs.STREAM_A, cplx)
+    assert np.array_equal(oracle_mod.tsmm(A, np.eye(M, dtype=dt)), A)
+    # C = e_i e_j^T moves column i of A into column j of B, zeros elsewhere
+    E = np.zeros((M, N), dt)
+    E[4, 2] = 1
+    Bsel = oracle_mod.tsmm(A, E)
+    assert np.array_equal(Bsel[:, 2], A[:, 4])
+    assert not np.any(np.delete(Bsel, 2, axis=1))
+    # K = 0 gives the zero matrix
+    Z = oracle_mod.tsmttsm(np.zeros((0, M), dt), np.zeros((0, N), dt))
+    assert Z.shape == (M, N) and not np.any(Z)
+    # M = N = 1 is the scalar product (Section 1.3): the exactly representable
+    # case x = y = 2^-j sums to a finite geometric series
+    x = np.array([[2.0 ** -j] for j in range(40)])
+    assert oracle_mod.tsmttsm(x, x)[0, 0] == float(sum(Fraction(1, 4 ** j) for j in range(40)))
+
+
+# --------------------------------------------------------------- invariants
+@pytest.mark.parametrize("cplx", [False, True])
+def test_symmetry_transpose_linearity(oracle_mod, cplx):
+    K, M, N = 5000, 9, 4
+    A = inputs.host_uniform(K, M, 7, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, N, 7, inputs.STREAM_B, cplx)
+    G = oracle_mod.tsmttsm(A, A)
+    assert np.array_equal(G, G.T)                       # A^T A symmetric, bit for bit
+    if cplx:
+        H = oracle_mod.tsmttsm(A, A, op="C")
+        assert np.array_equal(H, H.conj().T)            # A^H A Hermitian
+    C = oracle_mod.tsmttsm(A, B)
+    assert np.array_equal(C, oracle_mod.tsmttsm(B, A).T)  # (A^T B)^T = B^T A
+    assert np.array_equal(oracle_mod.tsmttsm(2 * A, B), 2 * C)
+    assert np.array_equal(oracle_mod.tsmttsm(A, 0.25 * B), 0.25 * C)
+    A2 = inputs.host_uniform(K, M, 8, inputs.STREAM_A, cplx)
+    lin = oracle_mod.tsmttsm(0.3 * A + 1.7 * A2, B, compensated=True)
+    ref = 0.3 * oracle_mod.tsmttsm(A, B, compensated=True) + 1.7 * oracle_mod.tsmttsm(A2, B, compensated=True)
+    assert np.linalg.norm(lin - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("conj", [False, True])
+def test_complex_equals_real_expansion(oracle_mod, conj):
+    K, M, N = 3000, 5, 6
+    A = inputs.host_uniform(K, M, 9, inputs.STREAM_A, True)
+    B = inputs.host_uniform(K, N, 9, inputs.STREAM_B, True)
+    C = oracle_mod.tsmttsm(A, B, op="C" if conj else "T", compensated=True)
+    Ar, Ai, Br, Bi = (np.ascontiguousarray(X) for X in (A.real, A.imag, B.real, B.imag))
+    s = -1.0 if conj else 1.0
+    T = lambda X, Y: oracle_mod.tsmttsm(X, Y, compensated=True)
+    Cr = T(Ar, Br) - s * T(Ai, Bi)
+    Ci = T(Ar, Bi) + s * T(Ai, Br)
+    assert np.linalg.norm(C - (Cr + 1j * Ci)) <= 1e-14 * np.linalg.norm(C)
+    # and TSMM: B = A C expands the same way
+    X = inputs.host_uniform(M, N, 9, inputs.STREAM_C, True)
+    P = oracle_mod.tsmm(A, X, conjA=conj)
+    Xr, Xi = np.ascontiguousarray(X.real), np.ascontiguousarray(X.imag)
+    Pr = oracle_mod.tsmm(Ar, Xr) - s * oracle_mod.tsmm(Ai, Xi)
+    Pi = oracle_mod.tsmm(Ar, Xi) + s * oracle_mod.tsmm(Ai, Xr)
+    assert np.linalg.norm(P - (Pr + 1j * Pi)) <= 1e-14 * np.linalg.norm(P)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tsmm_row_by_row(oracle_mod, cplx):
+    K, M, N = 2000, 12, 7
+    A = inputs.host_uniform(K, M, 10, inputs.STREAM_A, cplx)
+    C = inputs.host_uniform(M, N, 10, inputs.STREAM_C, cplx)
+    B = oracle_mod.tsmm(A, C)
+    for k in (0, 1, 999, K - 1):
+        row = np.array([np.dot(A[k], C[:, n]) for n in range(N)])
+        assert np.allclose(B[k], row, rtol=0, atol=4 * M * U * np.max(np.abs(A[k])) * np.max(np.abs(C)) * M)
+
+
+# ------------------------------------------------------- library cross-check
+@pytest.mark.parametrize("M,N", [(1, 1), (4, 4), (32, 8), (8, 32), (64, 64)])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_numpy_blas_agreement(oracle_mod, M, N, cplx):
+    K = 20000
+    A = inputs.host_uniform(K, M, 11, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, N, 11, inputs.STREAM_B, cplx)
+    C = oracle_mod.tsmttsm(A, B, compensated=True)
+    assert np.linalg.norm(C - A.T @ B) <= 1e-13 * np.linalg.norm(C)
+    if cplx:
+        Ch = oracle_mod.tsmttsm(A, B, op="C", compensated=True)
+        assert np.linalg.norm(Ch - A.conj().T @ B) <= 1e-13 * np.linalg.norm(Ch)
+    X = inputs.host_uniform(M, N, 11, inputs.STREAM_C, cplx)
+    P = oracle_mod.tsmm(A, X)
+    assert np.linalg.norm(P - A @ X) <= 1e-14 * np.linalg.norm(P)
+
+
+# ------------------------------------------------------ layout and plumbing
+@pytest.mark.parametrize("cplx", [False, True])
+def test_leading_dimensions_and_beta_zero(oracle_mod, cplx):
+    dt = np.complex128 if cplx else np.float64
+    K, M, N = 333, 5, 3
+    A = inputs.host_uniform(K, M, 12, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, N, 12, inputs.STREAM_B, cplx)
+    Apad = np.full((K, M + 3), np.nan, dt)
+    Apad[:, :M] = A
+    Bpad = np.full((K, N + 2), np.nan, dt)
+    Bpad[:, :N] = B
+    assert np.array_equal(oracle_mod.tsmttsm(Apad[:, :M], Bpad[:, :N]), oracle_mod.tsmttsm(A, B))
+    C = inputs.host_uniform(M, N, 12, inputs.STREAM_C, cplx)
+    out = np.full((K, N + 2), np.nan, dt)
+    oracle_mod.tsmm(Apad[:, :M], C, out[:, :N])        # beta = 0: B_old (NaN) never read
+    assert np.array_equal(out[:, :N], oracle_mod.tsmm(A, C))
+    assert np.all(np.isnan(out[:, N:]))                 # padding untouched
+
+
+def test_thread_count_invariance(oracle_mod):
+    K, M, N = 50000, 16, 16
+    A = inputs.host_uniform(K, M, 13, inputs.STREAM_A)
+    B = inputs.host_uniform(K, N, 13, inputs.STREAM_B)
+    assert np.array_equal(oracle_mod.tsmttsm(A, B, nthreads=1), oracle_mod.tsmttsm(A, B, nthreads=7))
+    C = inputs.host_uniform(M, N, 13, inputs.STREAM_C)
+    assert np.array_equal(oracle_mod.tsmm(A, C, nthreads=1), oracle_mod.tsmm(A, C, nthreads=5))
+
+
+def test_entries_and_rows_helpers(oracle_mod):
+    K, M, N = 4000, 10, 6
+    A = inputs.host_uniform(K, M, 14, inputs.STREAM_A, True)
+    B = inputs.host_uniform(K, N, 14, inputs.STREAM_B, True)
+    full = oracle_mod.tsmttsm(A, B, op="C", compensated=True)
+    pairs = [(0, 0), (9, 5), (3, 2)]
+    ent = oracle_mod.tsmttsm_entries(A, B, pairs, op="C", compensated=True)
+    assert np.array_equal(ent, np.array([full[m, n] for m, n in pairs]))
+    C = inputs.host_uniform(M, N, 14, inputs.STREAM_C, True)
+    rows = [1, 77, 3999]
+    assert np.array_equal(oracle_mod.tsmm_rows(A[rows], C), oracle_mod.tsmm(A, C)[rows])
+
+
+def test_orth_step_projects_out(oracle_mod):
+    K, M, N = 6000, 8, 4
+    V = inputs.orthonormal_block(K, M, 15)
+    W = inputs.host_uniform(K, N, 15, inputs.STREAM_W0)
+    C, Wn = oracle_mod.orth_step(V, W)
+    assert np.linalg.norm(V.T @ Wn) <= 1e-13 * np.linalg.norm(W)
+    assert np.linalg.norm(C - V.T @ W) <= 1e-13 * np.linalg.norm(C)
+
+
+def test_invalid_arguments_rejected(oracle_mod):
+    A = np.zeros((4, 3))
+    with pytest.raises(ValueError):
+        oracle_mod.tsmttsm(A, np.zeros((5, 2)))
+    with pytest.raises(TypeError):
+        oracle_mod.tsmttsm(A.astype(np.float32), A.astype(np.float32))
+    with pytest.raises(ValueError):
+        oracle_mod.tsmm(A, np.zeros((2, 2)))
