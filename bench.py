@@ -1,0 +1,189 @@
+"""Throughput of the tall & skinny products on one MI355X.
+
+One step is one pass of the plain width sweep: TSMTTSM (C = A^T B) and TSMM
+(B = A C) in real (D) and complex (Z) double precision, K = 2^24 rows,
+(M, N) in {(1,1), (2,2), (4,4), (8,8), (16,16), (32,32), (64,64), (32,8), (8,32)}:
+36 calls on inputs already resident in HBM (seeded uniform(-1, 1) data,
+generated on the device).  The value is the sweep's algorithmic bytes per
+second (Eq. 1 of the paper: every element of A, B and C moves once); the JSON
+line also carries each call's GB/s, GFLOP/s and fraction of the
+min(HBM, FP64) roofline, the roofline record of the dominant kernel and the
+CPU oracle timed on a bounded sample of the same sweep.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12        # B/s, MI355X HBM3E (published)
+FP64_PEAK = 78.6e12      # flop/s, MI355X FP64 vector and matrix (published)
+METRIC = "TSMTTSM/TSMM GB/s & % of roofline vs width; mixed/batched speedup vs FP64"
+WIDTHS = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8), (8, 32)]
+K_SWEEP = 1 << 24
+
+
+def algorithmic(op, cplx, K, M, N, beta=0.0):
+    """Bytes and flops one call must move / compute (Eq. 1: A, B and C each
+    cross the memory interface once; 2MNK flops, 4x for complex)."""
+    s = 16 if cplx else 8
+    byts = s * (K * M + K * N + M * N)
+    if op == "tsmm" and beta != 0.0:
+        byts += s * K * N
+    flops = (8 if cplx else 2) * M * N * K
+    return byts, flops
+
+
+def roofline_time(byts, flops, bw=HBM_PEAK, peak=FP64_PEAK):
+    return max(byts / bw, flops / peak)
+
+
+def cpu_baseline(K_sample):
+    import numpy as np
+
+    import oracle
+    from paper_1905_03136_amd import inputs
+    oracle.build()
+    threads = oracle.max_threads()
+    total_bytes = 0
+    t_total = 0.0
+    for cplx in (False, True):
+        A = inputs.host_uniform(K_sample, 64, 0, inputs.STREAM_A, cplx)
+        B = inputs.host_uniform(K_sample, 64, 0, inputs.STREAM_B, cplx)
+        Xfull = inputs.host_uniform(64, 64, 0, inputs.STREAM_C, cplx)
+        for (M, N) in WIDTHS:
+            a = np.ascontiguousarray(A[:, :M])
+            b = np.ascontiguousarray(B[:, :N])
+            X = np.ascontiguousarray(Xfull[:M, :N])
+            t0 = time.perf_counter()
+            oracle.tsmttsm(a, b)
+            t1 = time.perf_counter()
+            oracle.tsmm(a, X)
+            t2 = time.perf_counter()
+            t_total += t2 - t0
+            for op in ("tsmttsm", "tsmm"):
+                total_bytes += algorithmic(op, cplx, K_sample, M, N)[0]
+    return {"value": total_bytes / t_total / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "the same 36-call sweep (TSMTTSM+TSMM, D and Z, 9 widths) at K=%d rows instead of "
+                      "2^24; plain binary64 triple loop, threads over output rows; %.1f s" % (K_sample, t_total),
+            "seconds": t_total, "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 15, help="rows of the oracle sample (0 = skip)")
+    ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the products run on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1905_03136_amd import api, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
+    K = K_SWEEP
+    bufA = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_A, c, dev) for c in (False, True)}
+    bufB = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_B, c, dev) for c in (False, True)}
+    smallC = {c: inputs.device_uniform(64, 64, 0, inputs.STREAM_C, c, dev) for c in (False, True)}
+    calls = []
+    for cplx in (False, True):
+        flatA = bufA[cplx].reshape(-1)
+        flatB = bufB[cplx].reshape(-1)
+        for (M, N) in WIDTHS:
+            Av = flatA[:K * M].view(K, M)
+            Bv = flatB[:K * N].view(K, N)
+            Cout = torch.empty((M, N), dtype=bufA[cplx].dtype, device=dev)
+            Cin = smallC[cplx][:M, :N].contiguous()
+            calls.append(dict(op="tsmttsm", cplx=cplx, M=M, N=N,
+                              fn=(lambda Av=Av, Bv=Bv, Cout=Cout: api.tsmttsm(Av, Bv, out=Cout))))
+            calls.append(dict(op="tsmm", cplx=cplx, M=M, N=N,
+                              fn=(lambda Av=Av, Cin=Cin, Bv=Bv: api.tsmm(Av, Cin, out=Bv))))
+    for c in calls:
+        c["bytes"], c["flops"] = algorithmic(c["op"], c["cplx"], K, c["M"], c["N"])
+        c["kernel"] = api.kernel_name(c["op"], torch.complex128 if c["cplx"] else torch.float64, c["M"], c["N"])
+    step_bytes = sum(c["bytes"] for c in calls)
+
+    def step(events=None):
+        for i, c in enumerate(calls):
+            if events is not None:
+                events[i][0].record()
+            c["fn"]()
+            if events is not None:
+                events[i][1].record()
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done; timing %d steps" % a.steps, file=sys.stderr, flush=True)
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
+           for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    per = []
+    for i, c in enumerate(calls):
+        ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(a.steps)) / a.steps
+        t = ms * 1e-3
+        rt = roofline_time(c["bytes"], c["flops"])
+        per.append(dict(op=c["op"], dtype="Z" if c["cplx"] else "D", M=c["M"], N=c["N"], kernel=c["kernel"],
+                        us=round(ms * 1e3, 2), GBps=round(c["bytes"] / t / 1e9, 1),
+                        GFLOPs=round(c["flops"] / t / 1e9, 1), roof_frac=round(rt / t, 4),
+                        bound="fp64" if c["flops"] / FP64_PEAK > c["bytes"] / HBM_PEAK else "hbm"))
+    dom_i = max(range(len(per)), key=lambda i: per[i]["us"])
+    d = per[dom_i]
+    dc = calls[dom_i]
+    dt = d["us"] * 1e-6
+    if d["bound"] == "hbm":
+        roof = {"bound": "hbm", "achieved": round(dc["bytes"] / dt / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": round(dc["bytes"] / dt / HBM_PEAK, 4)}
+    else:
+        roof = {"bound": "mfma", "achieved": round(dc["flops"] / dt / 1e12, 2), "peak": FP64_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": round(dc["flops"] / dt / FP64_PEAK, 4)}
+    roof.update({"kernel": d["kernel"], "avg_us": d["us"], "traffic": None,
+                 "per_launch": "%s %s M=%d N=%d K=%d: %d algorithmic bytes, %d flops" % (
+                     d["op"], d["dtype"], d["M"], d["N"], K, dc["bytes"], dc["flops"])})
+
+    if not a.no_check:
+        # spot check of the timed buffers: one TSMTTSM entry against a direct FP64 dot product
+        Av = bufA[False].reshape(-1)[:K * 8].view(K, 8)
+        Bv = bufB[False].reshape(-1)[:K * 8].view(K, 8)
+        C = api.tsmttsm(Av, Bv)
+        ref = torch.dot(Av[:, 3].contiguous(), Bv[:, 5].contiguous())
+        assert abs(float(C[3, 5] - ref)) <= 1e-10 * float(torch.dot(Av[:, 3].abs(), Bv[:, 5].abs()))
+
+    out = {
+        "metric": METRIC, "value": round(step_bytes * a.steps / (t1 - t0) / 1e9, 1), "unit": "GB/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uniform(-1,1), generated on the device)",
+        "config": {"workload": "plain width sweep: TSMTTSM and TSMM, D and Z, K=2^24, "
+                               "(M,N) in {(1,1),(2,2),(4,4),(8,8),(16,16),(32,32),(64,64),(32,8),(8,32)}",
+                   "calls_per_step": len(calls), "K": K, "bytes_per_step": step_bytes},
+        "roofline": roof,
+        "widths": per,
+    }
+    if a.cpu_sample > 0:
+        print("[bench] timing the CPU oracle on a %d-row sample" % a.cpu_sample, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

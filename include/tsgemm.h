@@ -1,0 +1,158 @@
+/*
+ * tsgemm.h -- C ABI of libtsgemm, tall & skinny matrix products on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The two products follow the problem statement of Ernst, Hager, Thies and
+ * Wellein, "Performance Engineering for Real and Complex Tall & Skinny Matrix
+ * Multiplication Kernels on GPUs" (arXiv 1905.03136), Section 1.1:
+ *   A is K x M and B is K x N ("tall": K is the long dimension, "skinny":
+ *   M, N in [1, 64]); C is the small M x N matrix.
+ *   TSMTTSM:  C = A^T B          TSMM:  B = A C
+ * on row-major block vectors (Section 1.2: one row of a block vector holds
+ * one entry of each of its vectors), in real (D) and complex (Z) double
+ * precision.
+ *
+ * Layout (all matrices row-major, leading dimensions count ELEMENTS):
+ *   A(k, m) = A[k * lda + m],  B(k, n) = B[k * ldb + n],  C(m, n) = C[m * ldc + n]
+ * Complex elements are interleaved (re, im) pairs of the storage type.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers to matrices are DEVICE pointers owned by the caller; the library
+ *    never frees or retains them.  `stream` is a hipStream_t (NULL = the null
+ *    stream).
+ *  - Calls are stream-ordered and asynchronous: they return once the work is
+ *    enqueued.  A kernel fault surfaces at the caller's next synchronisation.
+ *  - All arguments are validated on the host before any HIP call; invalid
+ *    arguments return TSG_E_ARG or TSG_E_UNSUPPORTED and enqueue nothing.
+ *  - Every result is deterministic: the same inputs on the same device give
+ *    the same bits, run after run (the cross-block reduction has a fixed
+ *    order).
+ *  - The library owns a per-(device, stream) workspace that it allocates on
+ *    first need (hipMalloc) and keeps until tsg_finalize().  Growing it while
+ *    the stream is being captured into a graph is impossible and returns
+ *    TSG_E_CAPTURE; call the operation once outside capture (or tsg_reserve)
+ *    first.  Calls that run concurrently on different streams use different
+ *    workspaces; calls on one stream are ordered by the stream.
+ *  - No C++ exception crosses this interface.  tsg_last_error() gives a
+ *    thread-local text for the last non-OK status of the calling thread.
+ */
+#ifndef TSGEMM_H
+#define TSGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage type of the tall matrices A and B.
+ * TSG_R64 / TSG_C128 are the paper's D and Z types (Section 1.1).
+ * TSG_R32 / TSG_C64 are the precision form: A and B are stored in binary32
+ * (halving the HBM traffic) while the small matrix C stays binary64 /
+ * complex128; see tsg_tsmttsm and tsg_tsmm for the arithmetic. */
+typedef enum {
+    TSG_R64 = 0,
+    TSG_C128 = 1,
+    TSG_R32 = 2,
+    TSG_C64 = 3
+} tsg_dtype;
+
+/* op(A) of TSMTTSM: the transpose, or for complex types the conjugate
+ * transpose (the Hermitian product A^H B that Gram-Schmidt orthogonalisation
+ * needs, Section 1.2).  TSG_OP_C on a real type is the same as TSG_OP_T. */
+typedef enum {
+    TSG_OP_T = 0,
+    TSG_OP_C = 1
+} tsg_op;
+
+typedef enum {
+    TSG_OK = 0,
+    TSG_E_ARG = 1,          /* invalid argument (sizes, strides, pointers, alignment) */
+    TSG_E_UNSUPPORTED = 2,  /* valid but outside the supported range (M or N > 64)    */
+    TSG_E_NOMEM = 3,        /* workspace allocation failed or exceeds TSG_MAX_WORKSPACE */
+    TSG_E_HIP = 4,          /* a HIP runtime call failed (no device, launch failure)  */
+    TSG_E_CAPTURE = 5       /* workspace must grow while the stream is being captured */
+} tsg_status;
+
+/*
+ * TSMTTSM (Section 3; Listing 1 defines the sum):
+ *   C[m * ldc + n] = sum_{k=0}^{K-1} op(A(k, m)) * B(k, n),   0 <= m < M, 0 <= n < N
+ * C is overwritten (never read).  K = 0 writes zeros.
+ *
+ * dt       storage type of A and B.  C is double (TSG_R64, TSG_R32) or
+ *          interleaved complex double (TSG_C128, TSG_C64).
+ * op       TSG_OP_T or TSG_OP_C (conjugates A; complex types only).
+ * K        rows of A and B, K >= 0 (64-bit; any size that fits in memory).
+ * M, N     columns of A and B, 1 <= M, N <= 64 (else TSG_E_UNSUPPORTED).
+ * A, lda   device pointer and leading dimension, lda >= M.
+ * B, ldb   device pointer and leading dimension, ldb >= N.
+ * C, ldc   device pointer and leading dimension, ldc >= N.
+ * Pointers must be aligned to the storage element size (8 B for TSG_R64,
+ * 16 B for TSG_C128, 4 B for TSG_R32, 8 B for TSG_C64) and may be NULL only
+ * when K == 0 (A, B).  C must not overlap A or B.
+ *
+ * Arithmetic: binary64 fused multiply-adds for TSG_R64 / TSG_C128.  For the
+ * precision form (TSG_R32 / TSG_C64) every product of two binary32 numbers is
+ * formed exactly, short runs of them are summed in binary32 with an
+ * error-free transformation (a compensated sum), and every run is folded
+ * into binary64 partial sums; the reduction across threads and blocks is in
+ * binary64.
+ */
+tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
+                       const void *A, int64_t lda, const void *B, int64_t ldb,
+                       void *C, int64_t ldc, void *stream);
+
+/*
+ * TSMM (Section 4):
+ *   B(k, n) = alpha * sum_{m=0}^{M-1} opA(A(k, m)) * C[m * ldc + n] + beta * B(k, n)
+ * opA conjugates A when conjA != 0 (complex types only).  alpha and beta are
+ * real.  beta == 0 means B is not read (NaNs in B do not propagate); the
+ * paper's TSMM is alpha = 1, beta = 0.
+ *
+ * dt       storage type of A and B; C is double / complex double as above.
+ * K        rows of A and B, K >= 0; K = 0 does nothing.
+ * M, N     1 <= M, N <= 64.
+ * A, lda   lda >= M.     C, ldc  ldc >= N (C is M x N).     B, ldb  ldb >= N.
+ * Alignment as for tsg_tsmttsm.  B must not overlap A or C.
+ *
+ * Arithmetic: binary64 fused multiply-adds; for the precision form the
+ * binary32 inputs are widened exactly, the sum over m is taken in binary64
+ * and the result is rounded once to binary32.
+ */
+tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N,
+                    const void *A, int64_t lda, const void *C, int64_t ldc,
+                    void *B, int64_t ldb, double alpha, double beta, void *stream);
+
+/* Make sure the workspace of (current device, stream) can serve a TSMTTSM of
+ * this shape without allocating, e.g. before capturing the stream into a
+ * graph.  May allocate (hipMalloc); returns TSG_E_CAPTURE if the stream is
+ * being captured and the workspace is too small. */
+tsg_status tsg_reserve(tsg_dtype dt, int64_t K, int32_t M, int32_t N, void *stream);
+
+/* Bytes of workspace a TSMTTSM of this shape uses on the current device. */
+size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N);
+
+/* Optional set-up for `device` (queries device properties); calls do it
+ * lazily otherwise.  Returns TSG_E_HIP without a usable device. */
+tsg_status tsg_init(int32_t device);
+
+/* Free every workspace of every device.  No call may be in flight. */
+void tsg_finalize(void);
+
+/* Static text for a status code. */
+const char *tsg_status_string(tsg_status s);
+
+/* Thread-local description of the calling thread's last error ("" if none). */
+const char *tsg_last_error(void);
+
+/* Name of the kernel variant the library would launch for this problem
+ * (diagnostics and profiling).  op_kind: 0 = TSMTTSM, 1 = TSMM.  Returns a
+ * static string, "" if the shape is invalid. */
+const char *tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t M, int32_t N);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSGEMM_H */

@@ -1,1 +1,13 @@
-"""MI355X (gfx950) tall & skinny matrix products: TSMTTSM C = A^T B and TSMM B = A C."""
+"""MI355X (gfx950) tall & skinny matrix products: TSMTTSM C = A^T B and TSMM B = A C.
+
+The products run in the HIP kernels of ``libtsgemm.so`` (C ABI in
+include/tsgemm.h); this package only marshals torch tensors into that ABI.
+Importing the torch API requires the built library.
+"""
+
+
+def __getattr__(name):
+    if name in ("tsmttsm", "tsmm", "kernel_name"):
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

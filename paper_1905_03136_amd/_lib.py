@@ -1,0 +1,101 @@
+"""ctypes binding of libtsgemm (declared in include/tsgemm.h), same names.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the shared library.  Importing this module fails loudly when the
+library has not been built; there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TSG_LIBRARY", os.path.join(HERE, "libtsgemm.so"))
+
+TSG_R64, TSG_C128, TSG_R32, TSG_C64 = 0, 1, 2, 3
+TSG_OP_T, TSG_OP_C = 0, 1
+TSG_OK, TSG_E_ARG, TSG_E_UNSUPPORTED, TSG_E_NOMEM, TSG_E_HIP, TSG_E_CAPTURE = range(6)
+STATUS_NAMES = {0: "TSG_OK", 1: "TSG_E_ARG", 2: "TSG_E_UNSUPPORTED", 3: "TSG_E_NOMEM", 4: "TSG_E_HIP",
+                5: "TSG_E_CAPTURE"}
+
+# exported symbols and their prototypes, in the order of include/tsgemm.h
+_i32, _i64, _vp, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
+PROTOTYPES = {
+    "tsg_tsmttsm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "tsg_tsmm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
+    "tsg_reserve": (_i32, [_i32, _i64, _i32, _i32, _vp]),
+    "tsg_workspace_size": (_sz, [_i32, _i64, _i32, _i32]),
+    "tsg_init": (_i32, [_i32]),
+    "tsg_finalize": (None, []),
+    "tsg_status_string": (ctypes.c_char_p, [_i32]),
+    "tsg_last_error": (ctypes.c_char_p, []),
+    "tsg_kernel_name": (ctypes.c_char_p, [_i32, _i32, _i32, _i32, _i32]),
+}
+
+
+class TsgError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), detail))
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libtsgemm.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_1905_03136_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def check(status):
+    if status != TSG_OK:
+        raise TsgError(status, lib().tsg_last_error().decode())
+    return status
+
+
+def tsg_tsmttsm(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream):
+    return lib().tsg_tsmttsm(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream)
+
+
+def tsg_tsmm(dt, conjA, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream):
+    return lib().tsg_tsmm(dt, conjA, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream)
+
+
+def tsg_reserve(dt, K, M, N, stream):
+    return lib().tsg_reserve(dt, K, M, N, stream)
+
+
+def tsg_workspace_size(dt, K, M, N):
+    return lib().tsg_workspace_size(dt, K, M, N)
+
+
+def tsg_init(device):
+    return lib().tsg_init(device)
+
+
+def tsg_finalize():
+    lib().tsg_finalize()
+
+
+def tsg_status_string(s):
+    return lib().tsg_status_string(s).decode()
+
+
+def tsg_last_error():
+    return lib().tsg_last_error().decode()
+
+
+def tsg_kernel_name(op_kind, dt, conj, M, N):
+    return lib().tsg_kernel_name(op_kind, dt, conj, M, N).decode()

@@ -1,0 +1,84 @@
+"""torch-facing entry points.  torch supplies device memory and streams only;
+the arithmetic runs in libtsgemm's HIP kernels (see ``_lib``)."""
+import torch
+
+from . import _lib
+
+_DT = {torch.float64: _lib.TSG_R64, torch.complex128: _lib.TSG_C128,
+       torch.float32: _lib.TSG_R32, torch.complex64: _lib.TSG_C64}
+_SMALL = {torch.float64: torch.float64, torch.complex128: torch.complex128,
+          torch.float32: torch.float64, torch.complex64: torch.complex128}
+
+
+def _ld(X, name):
+    if X.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if X.numel() == 0:
+        return max(1, X.size(1))
+    if X.size(1) > 1 and X.stride(1) != 1:
+        raise ValueError("%s must have unit column stride (row-major)" % name)
+    if X.size(0) <= 1:
+        return max(X.size(1), X.stride(0) if X.size(0) == 1 else X.size(1))
+    return X.stride(0)
+
+
+def _stream(dev):
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def tsmttsm(A, B, op="T", out=None):
+    """C = op(A)^T B for tall row-major A (K x M) and B (K x N) on the GPU.
+
+    op: 'T' (transpose) or 'C' (conjugate transpose, complex only).
+    float32 / complex64 inputs are the precision form; C is always float64 /
+    complex128.  ``out`` may be an (M x N) row-major tensor to write into.
+    """
+    if A.dtype != B.dtype or A.dtype not in _DT:
+        raise TypeError("A and B must share one of float64, complex128, float32, complex64")
+    if A.device != B.device or A.device.type != "cuda":
+        raise ValueError("A and B must be on the same GPU")
+    K, M = A.shape
+    if B.shape[0] != K:
+        raise ValueError("A and B must have the same number of rows")
+    N = B.shape[1]
+    if out is None:
+        out = torch.empty((M, N), dtype=_SMALL[A.dtype], device=A.device)
+    elif out.shape != (M, N) or out.dtype != _SMALL[A.dtype] or out.device != A.device:
+        raise ValueError("out must be an (M, N) %s tensor on %s" % (_SMALL[A.dtype], A.device))
+    with torch.cuda.device(A.device):
+        _lib.check(_lib.tsg_tsmttsm(_DT[A.dtype], _lib.TSG_OP_C if op == "C" else _lib.TSG_OP_T, K, M, N,
+                                    A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                    out.data_ptr(), _ld(out, "out"), _stream(A.device)))
+    return out
+
+
+def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False):
+    """B = alpha * op(A) C + beta * out for tall A (K x M) and small C (M x N).
+
+    Writes into ``out`` (K x N, A's dtype) when given, else into a new tensor
+    (beta must then be 0).  C is float64 / complex128 for every storage type.
+    """
+    if A.dtype not in _DT or C.dtype != _SMALL[A.dtype]:
+        raise TypeError("unsupported dtype combination %s, %s" % (A.dtype, C.dtype))
+    if A.device != C.device or A.device.type != "cuda":
+        raise ValueError("A and C must be on the same GPU")
+    K, M = A.shape
+    if C.shape[0] != M:
+        raise ValueError("C must have M rows")
+    N = C.shape[1]
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty((K, N), dtype=A.dtype, device=A.device)
+    elif out.shape != (K, N) or out.dtype != A.dtype or out.device != A.device:
+        raise ValueError("out must be a (K, N) %s tensor on %s" % (A.dtype, A.device))
+    with torch.cuda.device(A.device):
+        _lib.check(_lib.tsg_tsmm(_DT[A.dtype], int(bool(conjA)), K, M, N, A.data_ptr(), _ld(A, "A"),
+                                 C.data_ptr(), _ld(C, "C"), out.data_ptr(), _ld(out, "out"),
+                                 float(alpha), float(beta), _stream(A.device)))
+    return out
+
+
+def kernel_name(op, dtype, M, N, conj=False):
+    """Name of the kernel variant the library launches for this problem."""
+    return _lib.tsg_kernel_name(0 if op == "tsmttsm" else 1, _DT[dtype], int(conj), M, N)

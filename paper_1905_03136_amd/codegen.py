@@ -1,0 +1,229 @@
+"""Code generator: one gfx950 kernel variant per (operation, dtype, M, N).
+
+Section 2.1 of the paper argues for generating the code of every matrix size
+instead of writing one generic kernel: with the widths known at compile time
+the small loops unroll completely, the accumulators become plain registers and
+guard statements remain only where a tile does not divide the width.  Here the
+kernel bodies are HIP templates (``csrc/tsg_kernels.hpp``) whose widths are
+template arguments; this module decides the configuration of each variant
+(mapping, tile, rows in flight, waves per block), writes the explicit
+instantiations with their launchers and a registry table, and is run by the
+build before compiling.  Widths that are not pre-generated are served by
+run-time-width variants of the same templates, which keep the guards.
+
+A configuration can be overridden by the autotuner's table (``tuned.json``).
+"""
+import json
+import math
+import os
+
+DTYPES = {"r64": (0, False), "c128": (1, True)}
+OPS = {"tsmttsm": 0, "tsmm": 1}
+
+# widths of the plain sweep and the square widths of the target range
+GRADED = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8), (8, 32)]
+SQUARE_ALL = [(w, w) for w in range(1, 65)]
+
+WPB = 4  # waves per block
+
+
+def _ceil(a, b):
+    return -(-a // b)
+
+
+# ------------------------------------------------------------ configurations
+def default_config(op, dt, M, N):
+    """Heuristic configuration of one variant (the autotuner may replace it).
+
+    Register budget per lane is counted in doubles (2 VGPRs each); the FP64
+    VALU and MFMA operands must live in the 256 architectural VGPRs.
+    """
+    cw = 2 if DTYPES[dt][1] else 1
+    cplx = DTYPES[dt][1]
+    if op == "tsmttsm":
+        if M * N * cw <= 64 and (M + N) * cw <= 24:
+            u = max(1, min(4, (96 - M * N * cw) // (2 * (M + N) * cw)))
+            return dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
+                        VB=int(not cplx and N % 2 == 0), WPB=WPB)
+        mbt, nb = _ceil(M, 16), _ceil(N, 16)
+        mw = 1 if mbt * nb * 4 * cw <= 64 or mbt == 1 else 2
+        mb = _ceil(mbt, mw)
+        u = max(1, min(4, 16 // ((mb + nb) * cw)))
+        return dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)
+    if M * cw <= 8 and N * cw <= 8:
+        u = max(1, min(4, 16 // (M * cw)))
+        return dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
+                    VB=int(not cplx and N % 2 == 0), WPB=WPB)
+    ms, nb = _ceil(M, 4), _ceil(N, 16)
+    u = 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1
+    return dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)
+
+
+def generic_variants():
+    """Run-time-width variants: every (M, N) in [1, 64]^2 is served by one."""
+    out = []
+    for dt, (_, cplx) in DTYPES.items():
+        cw = 2 if cplx else 1
+        # TSMTTSM
+        for mx in ((4, 8) if not cplx else (4,)):
+            out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=mx, maxN=mx,
+                            cfg=dict(kind="valu", MX=mx, NX=mx, U=1, VA=0, VB=0, WPB=WPB)))
+        for mbt, nb in ((1, 1), (1, 2), (2, 1), (2, 2), (1, 4), (4, 1), (2, 4), (4, 2), (4, 4)):
+            mw = 1 if mbt * nb * 4 * cw <= 64 or mbt == 1 else 2
+            mb = _ceil(mbt, mw)
+            u = max(1, min(4, 16 // ((mb + nb) * cw)))
+            out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
+                            cfg=dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)))
+        # TSMM
+        for mx in ((4, 8) if not cplx else (4,)):
+            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=mx,
+                            cfg=dict(kind="valu", MX=mx, NX=mx, U=2, VA=0, VB=0, WPB=WPB)))
+        for ms in (4, 8, 16):
+            for nb in (1, 2, 4):
+                u = 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1
+                out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb,
+                                cfg=dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)))
+    return out
+
+
+def load_tuned(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            tab = json.load(f)
+        return {(e["op"], e["dt"], int(e["M"]), int(e["N"])): e["cfg"] for e in tab.get("entries", [])}
+    return {}
+
+
+def exact_variants(widths, tuned=None):
+    tuned = tuned or {}
+    out = []
+    for op in OPS:
+        for dt in DTYPES:
+            for (M, N) in widths:
+                cfg = tuned.get((op, dt, M, N)) or default_config(op, dt, M, N)
+                out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=cfg))
+    return out
+
+
+# ------------------------------------------------------------------ emission
+def variant_name(v):
+    c = v["cfg"]
+    w = "%dx%d" % (v["M"], v["N"]) if v["M"] else "le%dx%d" % (v["maxM"], v["maxN"])
+    if c["kind"] == "valu":
+        tag = "valu_u%d" % c["U"]
+    elif v["op"] == "tsmttsm":
+        tag = "mfma_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
+    else:
+        tag = "mfma_s%dn%d_u%d" % (c["MS"], c["NB"], c["U"])
+    return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
+
+
+def _template(v):
+    c = v["cfg"]
+    cplx = "true" if DTYPES[v["dt"]][1] else "false"
+    M, N = v["M"], v["N"]
+    if v["op"] == "tsmttsm":
+        if c["kind"] == "valu":
+            return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
+                M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
+                "true" if c["VB"] else "false", c["WPB"])
+        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"])
+    if c["kind"] == "valu":
+        return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
+            M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
+            "true" if c["VB"] else "false", c["WPB"])
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d>" % (M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"])
+
+
+def rows_per_tile(v):
+    c = v["cfg"]
+    if v["op"] == "tsmttsm":
+        return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])
+    return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 16 * c["U"] * c["WPB"]
+
+
+def _launcher(v, fn):
+    tmpl = _template(v)
+    threads = 64 * v["cfg"]["WPB"]
+    if v["op"] == "tsmttsm":
+        args = "p.K, p.M, p.N, p.A, p.lda, p.X, p.ldx, static_cast<double*>(p.Y), p.ldy, p.ws, p.cnt, p.conj"
+    else:
+        args = ("p.K, p.M, p.N, p.A, p.lda, static_cast<const double*>(p.X), p.ldx, p.Y, p.ldy, "
+                "p.alpha, p.beta, p.conj")
+    return ("void %s(const tsg::Launch& p)\n{\n"
+            "    hipLaunchKernelGGL((%s), dim3(p.grid), dim3(%d), 0, p.stream, %s);\n}\n"
+            "const void* %s() { return reinterpret_cast<const void*>(&%s); }\n"
+            % (fn, tmpl, threads, args, fn.replace("launch_", "kernel_"), tmpl))
+
+
+def _record(v, fn):
+    c = v["cfg"]
+    pair_a = int(c["kind"] == "valu" and bool(c.get("VA")))
+    pair_x = int(c["kind"] == "valu" and bool(c.get("VB")))
+    even = int(v["M"] == 0 and (pair_a or pair_x))
+    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
+            % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
+               64 * c["WPB"], rows_per_tile(v), variant_name(v), fn.replace("launch_", "kernel_"), fn))
+
+
+def emit(outdir, variants, per_file=6):
+    """Write gen/tsg_gen_XX.hip (instantiations + launchers) and gen/tsg_table.hip.
+    Returns the list of written source files.  Files are only rewritten when
+    their text changes, so unchanged units need no recompilation."""
+    os.makedirs(outdir, exist_ok=True)
+    files = []
+    recs = []
+    decls = []
+    nfiles = max(1, math.ceil(len(variants) / per_file))
+    for fi in range(nfiles):
+        chunk = variants[fi * per_file:(fi + 1) * per_file]
+        body = ['// generated by codegen.py -- do not edit\n#include "../tsg_kernels.hpp"\n'
+                '#include "../tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
+        for k, v in enumerate(chunk):
+            fn = "launch_%s" % variant_name(v)
+            body.append(_launcher(v, fn))
+            decls.append("void %s(const tsg::Launch& p);\nconst void* %s();\n" % (fn, fn.replace("launch_", "kernel_")))
+            recs.append((v, fn))
+        body.append("}  // namespace tsg_gen\n")
+        text = "".join(body)
+        path = os.path.join(outdir, "tsg_gen_%02d.hip" % fi)
+        _write_if_changed(path, text)
+        files.append(path)
+    table = ['// generated by codegen.py -- do not edit\n#include "../tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
+    table.extend(decls)
+    table.append("}  // namespace tsg_gen\n\n// host-only object: keep it out of the device compilation pass\n"
+                 "#ifndef __HIP_DEVICE_COMPILE__\nnamespace tsg {\nusing namespace tsg_gen;\n"
+                 "const Variant kVariants[] = {\n")
+    for v, fn in recs:
+        table.append(_record(v, fn))
+    table.append("};\nconst int kNumVariants = %d;\n}  // namespace tsg\n#endif\n" % len(recs))
+    path = os.path.join(outdir, "tsg_table.hip")
+    _write_if_changed(path, "".join(table))
+    files.append(path)
+    # remove stale units from an earlier, larger variant set
+    for f in os.listdir(outdir):
+        p = os.path.join(outdir, f)
+        if f.startswith("tsg_gen_") and p not in files:
+            os.remove(p)
+    return files
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path):
+        with open(path) as f:
+            if f.read() == text:
+                return
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def all_variants(widths=None, tuned_path=None):
+    widths = (GRADED + SQUARE_ALL) if widths is None else widths
+    seen = set()
+    uniq = []
+    for (M, N) in widths:
+        if (M, N) not in seen:
+            seen.add((M, N))
+            uniq.append((M, N))
+    return exact_variants(uniq, load_tuned(tuned_path)) + generic_variants()

@@ -1,0 +1,49 @@
+// tsg_registry.hpp -- host-side description of the generated kernel variants.
+// The code generator emits one Variant record (and one launcher) per
+// instantiated kernel; the runtime picks a record for each call.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsg {
+
+// Arguments of one launch.  For TSMTTSM, X/ldx is B and Y/ldy is C; for TSMM,
+// X/ldx is C and Y/ldy is B.
+struct Launch {
+    hipStream_t stream;
+    int grid;
+    int64_t K;
+    int M, N;
+    int conj;
+    const void* A;
+    int64_t lda;
+    const void* X;
+    int64_t ldx;
+    void* Y;
+    int64_t ldy;
+    double alpha, beta;
+    double* ws;
+    unsigned* cnt;
+};
+
+enum OpKind { OP_TSMTTSM = 0, OP_TSMM = 1 };
+
+struct Variant {
+    int op;             // OpKind
+    int dt;             // tsg_dtype of the tall matrices
+    int M, N;           // exact widths served, or 0 for a run-time-width variant
+    int maxM, maxN;     // largest widths served (run-time-width variants)
+    int pairA;          // needs 16-byte paired loads of A (even lda, aligned A)
+    int pairX;          // TSMTTSM: paired loads of B; TSMM: paired stores of B
+    int evenW;          // run-time-width variant that needs even widths (paired access)
+    int threads;        // block size
+    int rows_per_tile;  // rows consumed by one block per grid-stride iteration
+    const char* name;
+    const void* (*kernel)(); // device function, for occupancy queries
+    void (*launch)(const Launch&);
+};
+
+extern const Variant kVariants[];
+extern const int kNumVariants;
+
+}  // namespace tsg

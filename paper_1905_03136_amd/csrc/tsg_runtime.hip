@@ -1,0 +1,378 @@
+// tsg_runtime.hip -- host side of libtsgemm: argument validation, choice of
+// the kernel variant, per-(device, stream) workspace, grid sizing and launch.
+// The C ABI is declared in include/tsgemm.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tsgemm.h"
+#include "tsg_registry.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+tsg_status fail(tsg_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+constexpr int kMaxWidth = 64;
+constexpr int kGroup = 16;          // must equal tsg::kGroup in tsg_device.hpp
+constexpr int kCounterSlots = 4096; // first-level counters + one second-level counter
+
+struct DeviceInfo {
+    int cus = 0;
+    bool ok = false;
+};
+
+struct Workspace {
+    void* data = nullptr;
+    size_t bytes = 0;
+    unsigned* counters = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_dev;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<std::pair<int, const tsg::Variant*>, int> g_occ;  // (device, variant) -> blocks per CU
+
+int is_complex(tsg_dtype dt) { return dt == TSG_C128 || dt == TSG_C64; }
+size_t elem_bytes(tsg_dtype dt)
+{
+    switch (dt) {
+    case TSG_R64: return 8;
+    case TSG_C128: return 16;
+    case TSG_R32: return 4;
+    case TSG_C64: return 8;
+    }
+    return 0;
+}
+
+tsg_status device_info(int dev, DeviceInfo* out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end() && it->second.ok) {
+        *out = it->second;
+        return TSG_OK;
+    }
+    DeviceInfo d;
+    hipError_t e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail(TSG_E_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    d.ok = true;
+    g_dev[dev] = d;
+    *out = d;
+    return TSG_OK;
+}
+
+tsg_status current_device(int* dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return fail(TSG_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    return TSG_OK;
+}
+
+int occupancy(int dev, const tsg::Variant& v)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, &v);
+    auto it = g_occ.find(key);
+    if (it != g_occ.end()) return it->second;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, v.kernel(), v.threads, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    g_occ[key] = blocks;
+    return blocks;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Choose the variant: the exact (op, dtype, M, N) one if its access
+// requirements hold, else the first run-time-width variant covering (M, N).
+const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int64_t lda, const void* X,
+                         int64_t ldx)
+{
+    const bool a_pairs = (lda % 2 == 0) && aligned(A, 16);
+    const bool x_pairs = (ldx % 2 == 0) && aligned(X, 16);
+    const tsg::Variant* best = nullptr;
+    for (int i = 0; i < tsg::kNumVariants; ++i) {
+        const tsg::Variant& v = tsg::kVariants[i];
+        if (v.op != op || v.dt != (int)dt) continue;
+        if (v.pairA && !a_pairs) continue;
+        if (v.pairX && !x_pairs) continue;
+        if (v.M == M && v.N == N) return &v;
+        if (v.M == 0 && !best && M <= v.maxM && N <= v.maxN && (!v.evenW || (M % 2 == 0 && N % 2 == 0)))
+            best = &v;
+    }
+    return best;
+}
+
+tsg_status get_workspace(int dev, hipStream_t stream, size_t bytes, Workspace** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    const char* lim = getenv("TSG_MAX_WORKSPACE");
+    if (lim && bytes > (size_t)strtoull(lim, nullptr, 10))
+        return fail(TSG_E_NOMEM, "workspace of %zu bytes exceeds TSG_MAX_WORKSPACE=%s", bytes, lim);
+    Workspace& w = g_ws[std::make_pair(dev, stream)];
+    if (w.counters && w.bytes >= bytes) {
+        *out = &w;
+        return TSG_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(TSG_E_CAPTURE, "workspace must grow to %zu bytes while the stream is captured; "
+                                   "run the call once before capture or use tsg_reserve", bytes);
+    hipError_t e;
+    if (!w.counters) {
+        e = hipMalloc(reinterpret_cast<void**>(&w.counters), kCounterSlots * sizeof(unsigned));
+        if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(counters): %s", hipGetErrorString(e));
+        e = hipMemset(w.counters, 0, kCounterSlots * sizeof(unsigned));
+        if (e != hipSuccess) return fail(TSG_E_HIP, "hipMemset(counters): %s", hipGetErrorString(e));
+    }
+    if (w.bytes < bytes) {
+        if (w.data) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fail(TSG_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+            hipFree(w.data);
+            w.data = nullptr;
+            w.bytes = 0;
+        }
+        size_t grow = bytes < (1u << 20) ? (1u << 20) : bytes;
+        e = hipMalloc(&w.data, grow);
+        if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+        w.bytes = grow;
+    }
+    *out = &w;
+    return TSG_OK;
+}
+
+tsg_status validate(tsg_dtype dt, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda, const void* X,
+                    int64_t ldx, const void* Y, int64_t ldy, int op)
+{
+    if (dt != TSG_R64 && dt != TSG_C128 && dt != TSG_R32 && dt != TSG_C64)
+        return fail(TSG_E_ARG, "unknown dtype %d", (int)dt);
+    if (K < 0) return fail(TSG_E_ARG, "K = %lld < 0", (long long)K);
+    if (M < 1 || N < 1) return fail(TSG_E_ARG, "M = %d, N = %d: widths must be >= 1", M, N);
+    if (M > kMaxWidth || N > kMaxWidth)
+        return fail(TSG_E_UNSUPPORTED, "M = %d, N = %d: widths above %d are not supported", M, N, kMaxWidth);
+    const size_t es = elem_bytes(dt);
+    if (op == tsg::OP_TSMTTSM) {
+        // A (K x M), X = B (K x N), Y = C (M x N)
+        if (lda < M) return fail(TSG_E_ARG, "lda = %lld < M = %d", (long long)lda, M);
+        if (ldx < N) return fail(TSG_E_ARG, "ldb = %lld < N = %d", (long long)ldx, N);
+        if (ldy < N) return fail(TSG_E_ARG, "ldc = %lld < N = %d", (long long)ldy, N);
+        if (!Y) return fail(TSG_E_ARG, "C is NULL");
+        if (K > 0 && (!A || !X)) return fail(TSG_E_ARG, "A or B is NULL");
+        if ((A && !aligned(A, es)) || (X && !aligned(X, es)))
+            return fail(TSG_E_ARG, "A and B must be aligned to %zu bytes", es);
+        if (!aligned(Y, is_complex(dt) ? 16 : 8)) return fail(TSG_E_ARG, "C must be aligned to its element size");
+    } else {
+        // A (K x M), X = C (M x N), Y = B (K x N)
+        if (lda < M) return fail(TSG_E_ARG, "lda = %lld < M = %d", (long long)lda, M);
+        if (ldx < N) return fail(TSG_E_ARG, "ldc = %lld < N = %d", (long long)ldx, N);
+        if (ldy < N) return fail(TSG_E_ARG, "ldb = %lld < N = %d", (long long)ldy, N);
+        if (K > 0 && (!A || !X || !Y)) return fail(TSG_E_ARG, "A, B or C is NULL");
+        if ((A && !aligned(A, es)) || (Y && !aligned(Y, es)))
+            return fail(TSG_E_ARG, "A and B must be aligned to %zu bytes", es);
+        if (X && !aligned(X, is_complex(dt) ? 16 : 8)) return fail(TSG_E_ARG, "C must be aligned to its element size");
+    }
+    if (dt == TSG_R32 || dt == TSG_C64)
+        return fail(TSG_E_UNSUPPORTED, "the binary32 storage types are not built into this library");
+    return TSG_OK;
+}
+
+int grid_for(int dev, const tsg::Variant& v, int64_t K, int cus)
+{
+    const int64_t tiles = (K + v.rows_per_tile - 1) / v.rows_per_tile;
+    const int64_t cap = (int64_t)cus * occupancy(dev, v);
+    int64_t g = tiles < cap ? tiles : cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+size_t tsmttsm_ws_bytes(int grid, int M, int N, bool cplx)
+{
+    const size_t E = (size_t)M * N * (cplx ? 2 : 1);
+    const size_t ng = (grid + kGroup - 1) / kGroup;
+    return grid > 1 ? (grid + ng) * E * sizeof(double) : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, void* stream)
+{
+    g_err.clear();
+    if (op != TSG_OP_T && op != TSG_OP_C) return fail(TSG_E_ARG, "unknown op %d", (int)op);
+    tsg_status s = validate(dt, K, M, N, A, lda, B, ldb, C, ldc, tsg::OP_TSMTTSM);
+    if (s != TSG_OK) return s;
+    int dev;
+    if ((s = current_device(&dev)) != TSG_OK) return s;
+    DeviceInfo di;
+    if ((s = device_info(dev, &di)) != TSG_OK) return s;
+    const tsg::Variant* v = pick(tsg::OP_TSMTTSM, dt, M, N, A, lda, B, ldb);
+    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMTTSM %dx%d", M, N);
+    tsg::Launch p{};
+    p.stream = static_cast<hipStream_t>(stream);
+    p.grid = grid_for(dev, *v, K, di.cus);
+    p.K = K;
+    p.M = M;
+    p.N = N;
+    p.conj = (op == TSG_OP_C && is_complex(dt)) ? 1 : 0;
+    p.A = A;
+    p.lda = lda;
+    p.X = B;
+    p.ldx = ldb;
+    p.Y = C;
+    p.ldy = ldc;
+    Workspace* w = nullptr;
+    if ((s = get_workspace(dev, p.stream, tsmttsm_ws_bytes(p.grid, M, N, is_complex(dt)), &w)) != TSG_OK)
+        return s;
+    if ((size_t)(p.grid + kGroup - 1) / kGroup + 1 > (size_t)kCounterSlots)
+        return fail(TSG_E_UNSUPPORTED, "grid of %d blocks exceeds the counter slots", p.grid);
+    p.ws = static_cast<double*>(w->data);
+    p.cnt = w->counters;
+    v->launch(p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
+    return TSG_OK;
+}
+
+tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
+                    const void* C, int64_t ldc, void* B, int64_t ldb, double alpha, double beta, void* stream)
+{
+    g_err.clear();
+    tsg_status s = validate(dt, K, M, N, A, lda, C, ldc, B, ldb, tsg::OP_TSMM);
+    if (s != TSG_OK) return s;
+    if (K == 0) return TSG_OK;
+    int dev;
+    if ((s = current_device(&dev)) != TSG_OK) return s;
+    DeviceInfo di;
+    if ((s = device_info(dev, &di)) != TSG_OK) return s;
+    const tsg::Variant* v = pick(tsg::OP_TSMM, dt, M, N, A, lda, B, ldb);
+    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMM %dx%d", M, N);
+    tsg::Launch p{};
+    p.stream = static_cast<hipStream_t>(stream);
+    p.grid = grid_for(dev, *v, K, di.cus);
+    p.K = K;
+    p.M = M;
+    p.N = N;
+    p.conj = (conjA && is_complex(dt)) ? 1 : 0;
+    p.A = A;
+    p.lda = lda;
+    p.X = C;
+    p.ldx = ldc;
+    p.Y = B;
+    p.ldy = ldb;
+    p.alpha = alpha;
+    p.beta = beta;
+    v->launch(p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
+    return TSG_OK;
+}
+
+size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N)
+{
+    if (M < 1 || N < 1 || M > kMaxWidth || N > kMaxWidth || K < 0) return 0;
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    DeviceInfo di;
+    if (device_info(dev, &di) != TSG_OK) return 0;
+    const tsg::Variant* v = pick(tsg::OP_TSMTTSM, dt, M, N, nullptr, M + (M & 1), nullptr, N + (N & 1));
+    if (!v) return 0;
+    return tsmttsm_ws_bytes(grid_for(dev, *v, K, di.cus), M, N, is_complex(dt));
+}
+
+tsg_status tsg_reserve(tsg_dtype dt, int64_t K, int32_t M, int32_t N, void* stream)
+{
+    g_err.clear();
+    if (M < 1 || N < 1 || K < 0) return fail(TSG_E_ARG, "invalid shape");
+    if (M > kMaxWidth || N > kMaxWidth) return fail(TSG_E_UNSUPPORTED, "widths above %d", kMaxWidth);
+    int dev;
+    tsg_status s = current_device(&dev);
+    if (s != TSG_OK) return s;
+    DeviceInfo di;
+    if ((s = device_info(dev, &di)) != TSG_OK) return s;
+    // the largest grid any TSMTTSM variant of this shape may use
+    size_t need = 0;
+    for (int i = 0; i < tsg::kNumVariants; ++i) {
+        const tsg::Variant& v = tsg::kVariants[i];
+        if (v.op != tsg::OP_TSMTTSM || v.dt != (int)dt) continue;
+        if (!((v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN))) continue;
+        size_t b = tsmttsm_ws_bytes(grid_for(dev, v, K, di.cus), M, N, is_complex(dt));
+        if (b > need) need = b;
+    }
+    Workspace* w;
+    return get_workspace(dev, static_cast<hipStream_t>(stream), need, &w);
+}
+
+tsg_status tsg_init(int32_t device)
+{
+    g_err.clear();
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(TSG_E_HIP, "no HIP device: %s", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(TSG_E_ARG, "device %d out of range [0, %d)", device, n);
+    DeviceInfo di;
+    return device_info(device, &di);
+}
+
+void tsg_finalize(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = -1;
+    hipGetDevice(&cur);
+    for (auto& kv : g_ws) {
+        hipSetDevice(kv.first.first);
+        if (kv.second.data) hipFree(kv.second.data);
+        if (kv.second.counters) hipFree(kv.second.counters);
+    }
+    g_ws.clear();
+    g_occ.clear();
+    if (cur >= 0) hipSetDevice(cur);
+}
+
+const char* tsg_status_string(tsg_status s)
+{
+    switch (s) {
+    case TSG_OK: return "TSG_OK";
+    case TSG_E_ARG: return "TSG_E_ARG: invalid argument";
+    case TSG_E_UNSUPPORTED: return "TSG_E_UNSUPPORTED: outside the supported range";
+    case TSG_E_NOMEM: return "TSG_E_NOMEM: workspace allocation failed";
+    case TSG_E_HIP: return "TSG_E_HIP: HIP runtime error";
+    case TSG_E_CAPTURE: return "TSG_E_CAPTURE: workspace cannot grow during stream capture";
+    }
+    return "unknown tsg_status";
+}
+
+const char* tsg_last_error(void) { return g_err.c_str(); }
+
+const char* tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t M, int32_t N)
+{
+    (void)conj;
+    if (op_kind != 0 && op_kind != 1) return "";
+    if (M < 1 || N < 1 || M > kMaxWidth || N > kMaxWidth) return "";
+    alignas(16) static const char buf16[16] = {0};
+    const void* al = static_cast<const void*>(buf16);
+    const tsg::Variant* v = pick(op_kind, dt, M, N, al, M + (M & 1), al, N + (N & 1));
+    return v ? v->name : "";
+}
+
+}  // extern "C"

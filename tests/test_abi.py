@@ -1,0 +1,106 @@
+"""The C-ABI library loads, exports every entry point declared in
+include/tsgemm.h, and validates arguments on the host before any HIP call.
+No compute call is made here (no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_03136_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsgemm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsg_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.lib()
+
+
+def test_header_declares_expected_api():
+    syms = declared_symbols()
+    for s in ("tsg_tsmttsm", "tsg_tsmm", "tsg_init", "tsg_finalize", "tsg_status_string", "tsg_last_error",
+              "tsg_workspace_size", "tsg_reserve", "tsg_kernel_name"):
+        assert s in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+        assert s in _lib.PROTOTYPES, "binding lacks a prototype for %s" % s
+
+
+def test_status_strings(lib):
+    for code, name in _lib.STATUS_NAMES.items():
+        assert _lib.tsg_status_string(code).startswith(name)
+
+
+A = 1 << 12   # fake, 16-byte aligned "device" addresses: validation fails before any use
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 0, -1, 4, 4, A, 4, A, 4, A, 4), _lib.TSG_E_ARG),          # K < 0
+    ((0, 0, 10, 0, 4, A, 4, A, 4, A, 4), _lib.TSG_E_ARG),          # M < 1
+    ((0, 0, 10, 4, 65, A, 4, A, 65, A, 65), _lib.TSG_E_UNSUPPORTED),  # N > 64
+    ((0, 0, 10, 4, 4, A, 3, A, 4, A, 4), _lib.TSG_E_ARG),          # lda < M
+    ((0, 0, 10, 4, 4, A, 4, A, 3, A, 4), _lib.TSG_E_ARG),          # ldb < N
+    ((0, 0, 10, 4, 4, A, 4, A, 4, A, 2), _lib.TSG_E_ARG),          # ldc < N
+    ((0, 0, 10, 4, 4, None, 4, A, 4, A, 4), _lib.TSG_E_ARG),       # A NULL
+    ((0, 0, 10, 4, 4, A, 4, A, 4, None, 4), _lib.TSG_E_ARG),       # C NULL
+    ((0, 0, 10, 4, 4, A + 4, 4, A, 4, A, 4), _lib.TSG_E_ARG),      # misaligned double
+    ((1, 0, 10, 4, 4, A + 8, 4, A, 4, A, 4), _lib.TSG_E_ARG),      # misaligned complex
+    ((7, 0, 10, 4, 4, A, 4, A, 4, A, 4), _lib.TSG_E_ARG),          # unknown dtype
+    ((0, 3, 10, 4, 4, A, 4, A, 4, A, 4), _lib.TSG_E_ARG),          # unknown op
+])
+def test_tsmttsm_validation(lib, args, code):
+    assert _lib.tsg_tsmttsm(*args, None) == code
+    assert _lib.tsg_last_error() != ""
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 0, -5, 4, 4, A, 4, A, 4, A, 4), _lib.TSG_E_ARG),
+    ((0, 0, 10, 65, 4, A, 65, A, 4, A, 4), _lib.TSG_E_UNSUPPORTED),
+    ((0, 0, 10, 4, 4, A, 2, A, 4, A, 4), _lib.TSG_E_ARG),          # lda < M
+    ((0, 0, 10, 4, 4, A, 4, A, 3, A, 4), _lib.TSG_E_ARG),          # ldc < N
+    ((0, 0, 10, 4, 4, A, 4, A, 4, A, 3), _lib.TSG_E_ARG),          # ldb < N
+    ((0, 0, 10, 4, 4, A, 4, None, 4, A, 4), _lib.TSG_E_ARG),       # C NULL
+    ((1, 1, 10, 4, 4, A, 4, A, 4, A + 8, 4), _lib.TSG_E_ARG),      # misaligned complex B
+])
+def test_tsmm_validation(lib, args, code):
+    assert _lib.tsg_tsmm(*args, 1.0, 0.0, None) == code
+
+
+def test_tsmm_k_zero_is_a_no_op_without_device(lib):
+    # K = 0 has nothing to do: valid arguments return OK without touching HIP
+    assert _lib.tsg_tsmm(0, 0, 0, 4, 4, None, 4, A, 4, None, 4, 1.0, 0.0, None) == _lib.TSG_OK
+
+
+def test_no_device_reports_hip_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _lib.tsg_tsmttsm(0, 0, 100, 4, 4, A, 4, A, 4, A, 4, None) == _lib.TSG_E_HIP
+    assert _lib.tsg_init(0) == _lib.TSG_E_HIP
+    assert _lib.tsg_workspace_size(0, 1 << 20, 4, 4) == 0
+
+
+def test_kernel_names_cover_all_widths(lib):
+    for op in (0, 1):
+        for dt in (_lib.TSG_R64, _lib.TSG_C128):
+            for M in (1, 3, 16, 17, 33, 63, 64):
+                for N in (1, 5, 16, 31, 64):
+                    assert _lib.tsg_kernel_name(op, dt, 0, M, N) != ""
+    assert _lib.tsg_kernel_name(0, 0, 0, 65, 1) == ""
+
+
+def test_precision_dtypes_reported_unsupported_until_built(lib):
+    # binary32 storage is declared in the ABI; the status tells whether it is built
+    st = _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A, 4, A, 4, A, 4, None)
+    assert st in (_lib.TSG_E_UNSUPPORTED, _lib.TSG_E_HIP)
