@@ -26,6 +26,7 @@ HBM_PEAK = 8.0e12        # B/s, MI355X HBM3E (published)
 FP64_PEAK = 78.6e12      # flop/s, MI355X FP64 vector and matrix (published)
 METRIC = "TSMTTSM/TSMM GB/s & % of roofline vs width; mixed/batched speedup vs FP64"
 WIDTHS = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8), (8, 32)]
+FLUSH_ORDER = [(64, 64), (1, 1), (32, 32), (2, 2), (16, 16), (4, 4), (32, 8), (8, 8), (8, 32)]
 K_SWEEP = 1 << 24
 
 
@@ -42,6 +43,31 @@ def algorithmic(op, cplx, K, M, N, beta=0.0):
 
 def roofline_time(byts, flops, bw=HBM_PEAK, peak=FP64_PEAK):
     return max(byts / bw, flops / peak)
+
+
+def measure_bs(torch, src, dst, nbytes=8 << 30, reps=5):
+    """Achievable bandwidth b_s on this GPU with the library's probes (the
+    paper's read-only sum and read+write stream, Section 1.6): the median of
+    `reps` timed passes over `nbytes` (far beyond the 256 MB Infinity Cache).
+    'copy' counts read plus written bytes."""
+    from paper_1905_03136_amd import _lib
+    s = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind in ("read", "copy"):
+        times = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if kind == "read":
+                _lib.check(_lib.tsg_stream_read(src.data_ptr(), nbytes, s))
+            else:
+                _lib.check(_lib.tsg_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, s))
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        t = sorted(times[1:])[reps // 2]
+        out[kind] = (nbytes if kind == "read" else 2 * nbytes) / t
+    return out
 
 
 def cpu_baseline(K_sample):
@@ -98,19 +124,24 @@ def main():
     bufA = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_A, c, dev) for c in (False, True)}
     bufB = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_B, c, dev) for c in (False, True)}
     smallC = {c: inputs.device_uniform(64, 64, 0, inputs.STREAM_C, c, dev) for c in (False, True)}
+    # Call order: per dtype all TSMTTSM widths, then all TSMM widths, each in
+    # FLUSH_ORDER (a wide call between any two narrow ones), so that no call
+    # finds the data of the call before it in the 256 MB Infinity Cache.
     calls = []
     for cplx in (False, True):
         flatA = bufA[cplx].reshape(-1)
         flatB = bufB[cplx].reshape(-1)
-        for (M, N) in WIDTHS:
-            Av = flatA[:K * M].view(K, M)
-            Bv = flatB[:K * N].view(K, N)
-            Cout = torch.empty((M, N), dtype=bufA[cplx].dtype, device=dev)
-            Cin = smallC[cplx][:M, :N].contiguous()
-            calls.append(dict(op="tsmttsm", cplx=cplx, M=M, N=N,
-                              fn=(lambda Av=Av, Bv=Bv, Cout=Cout: api.tsmttsm(Av, Bv, out=Cout))))
-            calls.append(dict(op="tsmm", cplx=cplx, M=M, N=N,
-                              fn=(lambda Av=Av, Cin=Cin, Bv=Bv: api.tsmm(Av, Cin, out=Bv))))
+        for op in ("tsmttsm", "tsmm"):
+            for (M, N) in FLUSH_ORDER:
+                Av = flatA[:K * M].view(K, M)
+                Bv = flatB[:K * N].view(K, N)
+                if op == "tsmttsm":
+                    Cout = torch.empty((M, N), dtype=bufA[cplx].dtype, device=dev)
+                    fn = (lambda Av=Av, Bv=Bv, Cout=Cout: api.tsmttsm(Av, Bv, out=Cout))
+                else:
+                    Cin = smallC[cplx][:M, :N].contiguous()
+                    fn = (lambda Av=Av, Cin=Cin, Bv=Bv: api.tsmm(Av, Cin, out=Bv))
+                calls.append(dict(op=op, cplx=cplx, M=M, N=N, fn=fn))
     for c in calls:
         c["bytes"], c["flops"] = algorithmic(c["op"], c["cplx"], K, c["M"], c["N"])
         c["kernel"] = api.kernel_name(c["op"], torch.complex128 if c["cplx"] else torch.float64, c["M"], c["N"])
@@ -127,7 +158,9 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    print("[bench] warmup done; timing %d steps" % a.steps, file=sys.stderr, flush=True)
+    bs = measure_bs(torch, bufA[True], bufB[True])
+    print("[bench] warmup done; b_s read %.0f GB/s, copy %.0f GB/s; timing %d steps"
+          % (bs["read"] / 1e9, bs["copy"] / 1e9, a.steps), file=sys.stderr, flush=True)
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
            for _ in range(a.steps)]
     torch.cuda.synchronize()
@@ -142,9 +175,11 @@ def main():
         ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(a.steps)) / a.steps
         t = ms * 1e-3
         rt = roofline_time(c["bytes"], c["flops"])
+        rt_bs = roofline_time(c["bytes"], c["flops"], bw=bs["read"] if c["op"] == "tsmttsm" else bs["copy"])
         per.append(dict(op=c["op"], dtype="Z" if c["cplx"] else "D", M=c["M"], N=c["N"], kernel=c["kernel"],
                         us=round(ms * 1e3, 2), GBps=round(c["bytes"] / t / 1e9, 1),
                         GFLOPs=round(c["flops"] / t / 1e9, 1), roof_frac=round(rt / t, 4),
+                        roof_frac_bs=round(rt_bs / t, 4),
                         bound="fp64" if c["flops"] / FP64_PEAK > c["bytes"] / HBM_PEAK else "hbm"))
     dom_i = max(range(len(per)), key=lambda i: per[i]["us"])
     d = per[dom_i]
@@ -177,6 +212,9 @@ def main():
                                "(M,N) in {(1,1),(2,2),(4,4),(8,8),(16,16),(32,32),(64,64),(32,8),(8,32)}",
                    "calls_per_step": len(calls), "K": K, "bytes_per_step": step_bytes},
         "roofline": roof,
+        "b_s": {"read_GBps": round(bs["read"] / 1e9, 1), "copy_GBps": round(bs["copy"] / 1e9, 1),
+                "note": "measured with the library's stream probes over 8 GiB; roof_frac_bs uses b_s "
+                        "(read for TSMTTSM, copy for TSMM) instead of the 8 TB/s spec"},
         "widths": per,
     }
     if a.cpu_sample > 0:

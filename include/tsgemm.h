@@ -151,6 +151,27 @@ const char *tsg_last_error(void);
  * static string, "" if the shape is invalid. */
 const char *tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t M, int32_t N);
 
+/* ---- bandwidth probes (define the achievable bandwidth b_s of the roofline) ----
+ * The paper measures b_s with a read-only thread-local sum (the TSMTTSM
+ * pattern) and a read + write stream (the TSMM pattern), Section 1.6, Table 1.
+ * tsg_stream_read reads `bytes` from device pointer x; tsg_stream_copy copies
+ * `bytes` from src to dst (non-overlapping).  Pointers must be 16-byte aligned
+ * and bytes a multiple of 16 (else TSG_E_ARG).  Asynchronous on `stream`; time
+ * them with events.  tsg_stream_read keeps a small internal sink buffer. */
+tsg_status tsg_stream_read(const void *x, size_t bytes, void *stream);
+tsg_status tsg_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* ---- tuning hooks (used by the autotuner; not needed for ordinary calls) ----
+ * The library holds many generated kernel variants; normally it picks the one
+ * tuned for (operation, dtype, M, N).  tsg_force_variant(name) makes the
+ * calling thread's following calls use the named variant instead (a call it
+ * cannot serve returns TSG_E_UNSUPPORTED); NULL or "" restores the automatic
+ * choice.  Returns TSG_E_ARG for an unknown name.  tsg_variant_count and
+ * tsg_variant_name(i) enumerate the compiled variants (static strings). */
+tsg_status tsg_force_variant(const char *name);
+int32_t tsg_variant_count(void);
+const char *tsg_variant_name(int32_t i);
+
 #ifdef __cplusplus
 }
 #endif

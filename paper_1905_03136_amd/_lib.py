@@ -28,6 +28,11 @@ PROTOTYPES = {
     "tsg_status_string": (ctypes.c_char_p, [_i32]),
     "tsg_last_error": (ctypes.c_char_p, []),
     "tsg_kernel_name": (ctypes.c_char_p, [_i32, _i32, _i32, _i32, _i32]),
+    "tsg_stream_read": (_i32, [_vp, _sz, _vp]),
+    "tsg_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
+    "tsg_force_variant": (_i32, [ctypes.c_char_p]),
+    "tsg_variant_count": (_i32, []),
+    "tsg_variant_name": (ctypes.c_char_p, [_i32]),
 }
 
 
@@ -99,3 +104,23 @@ def tsg_last_error():
 
 def tsg_kernel_name(op_kind, dt, conj, M, N):
     return lib().tsg_kernel_name(op_kind, dt, conj, M, N).decode()
+
+
+def tsg_force_variant(name):
+    return lib().tsg_force_variant(name.encode() if name else None)
+
+
+def tsg_variant_count():
+    return lib().tsg_variant_count()
+
+
+def tsg_variant_name(i):
+    return lib().tsg_variant_name(i).decode()
+
+
+def tsg_stream_read(x, nbytes, stream):
+    return lib().tsg_stream_read(x, nbytes, stream)
+
+
+def tsg_stream_copy(src, dst, nbytes, stream):
+    return lib().tsg_stream_copy(src, dst, nbytes, stream)

@@ -33,6 +33,7 @@ CFLAGS = [
 
 HEADERS = [os.path.join(CSRC, h) for h in ("tsg_device.hpp", "tsg_kernels.hpp", "tsg_registry.hpp")] + \
     [os.path.join(ROOT, "include", "tsgemm.h")]
+TUNE_LIB = os.path.join(HERE, "libtsgemm_tune.so")
 
 
 def _stale(obj, deps):
@@ -51,26 +52,32 @@ def _compile(src, obj, extra):
     return src
 
 
-def generate(widths=None):
+def generate(widths=None, variants=None, gen_dir=GEN):
     sys.path.insert(0, ROOT)
     from paper_1905_03136_amd import codegen
-    tuned = os.path.join(HERE, "tuned.json")
-    variants = codegen.all_variants(widths, tuned)
-    return codegen.emit(GEN, variants), variants
+    if variants is None:
+        variants = codegen.all_variants(widths, os.path.join(HERE, "tuned.json"))
+    return codegen.emit(gen_dir, variants), variants
 
 
-def build(widths=None, jobs=None, extra_flags=(), verbose=True):
-    srcs, variants = generate(widths)
-    srcs = list(srcs) + [os.path.join(CSRC, "tsg_runtime.hip")]
-    os.makedirs(OBJ, exist_ok=True)
+def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, lib_path=LIB, tag=""):
+    """Generate and compile.  ``variants`` replaces the product's variant set
+    (the autotuner builds all candidates this way into its own library,
+    objects and generated sources kept apart by ``tag``)."""
+    gen_dir = GEN + tag
+    obj_dir = OBJ + tag
+    srcs, variants = generate(widths, variants, gen_dir)
+    srcs = list(srcs) + [os.path.join(CSRC, "tsg_runtime.hip"), os.path.join(CSRC, "tsg_stream.hip")]
+    OBJD = obj_dir
+    os.makedirs(OBJD, exist_ok=True)
     objs = []
     todo = []
     for s in srcs:
-        o = os.path.join(OBJ, os.path.basename(s) + ".o")
+        o = os.path.join(OBJD, os.path.basename(s) + ".o")
         objs.append(o)
         if _stale(o, [s] + HEADERS + [os.path.abspath(__file__)]):
             todo.append((s, o))
-    for o in glob.glob(os.path.join(OBJ, "*.o")):
+    for o in glob.glob(os.path.join(OBJD, "*.o")):
         if o not in objs:
             os.remove(o)
     jobs = jobs or min(8, os.cpu_count() or 1)
@@ -82,14 +89,14 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True):
             for done in ex.map(lambda so: _compile(so[0], so[1], list(extra_flags)), todo):
                 if verbose:
                     print("[build]   %s" % os.path.relpath(done, ROOT), flush=True)
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", LIB + ".tmp", *objs]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", lib_path + ".tmp", *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stdout[-6000:])
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib_path + ".tmp", lib_path)
     if verbose:
-        print("[build] wrote %s" % os.path.relpath(LIB, ROOT), flush=True)
-    return LIB
+        print("[build] wrote %s" % os.path.relpath(lib_path, ROOT), flush=True)
+    return lib_path
 
 
 def main(argv=None):

@@ -32,28 +32,95 @@ def _ceil(a, b):
 
 
 # ------------------------------------------------------------ configurations
-def default_config(op, dt, M, N):
-    """Heuristic configuration of one variant (the autotuner may replace it).
+def _valu_regs(op, M, N, cw, u):
+    """Doubles of register state per lane of a VALU variant (accumulators plus
+    the two leap-frog operand sets)."""
+    if op == "tsmttsm":
+        return M * N * cw + 2 * u * (M + N) * cw
+    return 2 * u * M * cw + N * cw
 
-    Register budget per lane is counted in doubles (2 VGPRs each); the FP64
-    VALU and MFMA operands must live in the 256 architectural VGPRs.
-    """
+
+def _mfma_regs(op, M, N, cw, c):
+    if op == "tsmttsm":
+        return c["MB"] * c["NB"] * 4 * cw + 2 * c["U"] * (c["MB"] + c["NB"]) * cw
+    return 2 * c["U"] * c["MS"] * cw + c["U"] * c["NB"] * 4 * cw
+
+
+def candidates(op, dt, M, N):
+    """Every configuration the autotuner times for (op, dt, M, N), pruned by
+    a register model (the gfx950 analogue of the paper's register estimate
+    2 (T_M T_N + 2 (T_M + T_N) + 8), Section 5.2): FP64 operands live in the
+    256 architectural VGPRs, MFMA accumulators may use the AGPRs."""
     cw = 2 if DTYPES[dt][1] else 1
     cplx = DTYPES[dt][1]
+    out = []
     if op == "tsmttsm":
-        if M * N * cw <= 64 and (M + N) * cw <= 24:
-            u = max(1, min(4, (96 - M * N * cw) // (2 * (M + N) * cw)))
-            return dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
-                        VB=int(not cplx and N % 2 == 0), WPB=WPB)
-        mbt, nb = _ceil(M, 16), _ceil(N, 16)
-        mw = 1 if mbt * nb * 4 * cw <= 64 or mbt == 1 else 2
-        mb = _ceil(mbt, mw)
-        u = max(1, min(4, 16 // ((mb + nb) * cw)))
-        return dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)
+        if M <= 16 and N <= 16:
+            for u in (1, 2, 4, 8):
+                for w in (4, 8):
+                    out.append(dict(kind="packed", U=u, WPB=w))
+        if M * N * cw <= 64:
+            for u in (1, 2, 4):
+                if _valu_regs(op, M, N, cw, u) <= 110:
+                    out.append(dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
+                                    VB=int(not cplx and N % 2 == 0), WPB=WPB))
+        if M > 8 or N > 8:
+            mbt, nb = _ceil(M, 16), _ceil(N, 16)
+            for mw in (1, 2, 4):
+                if mbt % mw and mw > 1:
+                    continue
+                if mw > mbt:
+                    continue
+                mb = _ceil(mbt, mw)
+                for u in (1, 2, 4):
+                    for w in (4, 8):
+                        if w % mw:
+                            continue
+                        c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w)
+                        acc = mb * nb * 4 * cw
+                        # 512-thread blocks cap a lane at 256 registers in all
+                        acc_cap = 48 if w == 8 else 64
+                        if acc <= acc_cap and 2 * u * (mb + nb) * cw <= 48:
+                            out.append(c)
+        return out
     if M * cw <= 8 and N * cw <= 8:
-        u = max(1, min(4, 16 // (M * cw)))
-        return dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
-                    VB=int(not cplx and N % 2 == 0), WPB=WPB)
+        for u in (1, 2, 4):
+            out.append(dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
+                            VB=int(not cplx and N % 2 == 0), WPB=WPB))
+    if N <= 16 and M <= 16 and _ceil((16 // N) * M, 4) <= 16:
+        for u in (1, 2, 4):
+            for w in (4, 8):
+                out.append(dict(kind="packed", U=u, WPB=w))
+    if M >= 4 or N >= 16:
+        ms, nb = _ceil(M, 4), _ceil(N, 16)
+        for u in (1, 2, 4):
+            for w in (4, 8):
+                c = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)
+                if _mfma_regs(op, M, N, cw, c) <= 160:
+                    out.append(c)
+    return out
+
+
+def default_config(op, dt, M, N):
+    """Heuristic configuration of one variant when the autotuner has not
+    measured this (op, dt, M, N): row packing on the matrix cores for narrow
+    widths, the blocked matrix-core kernels otherwise."""
+    cw = 2 if DTYPES[dt][1] else 1
+    if op == "tsmttsm":
+        if M <= 16 and N <= 16 and (M < 16 or N < 16):
+            return dict(kind="packed", U=4, WPB=WPB)
+        mbt, nb = _ceil(M, 16), _ceil(N, 16)
+        mw = 1
+        while mbt * nb * 4 * cw > 32 * mw and mw < mbt:
+            mw *= 2
+        mb = _ceil(mbt, mw)
+        u = max(1, min(4, 8 // ((mb + nb) * cw)))
+        return dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)
+    if M * cw <= 2 and N * cw <= 2:
+        return dict(kind="valu", MX=M, NX=N, U=4, VA=int(cw == 1 and M % 2 == 0),
+                    VB=int(cw == 1 and N % 2 == 0), WPB=WPB)
+    if N <= 16 and M <= 16 and _ceil((16 // N) * M, 4) <= 16 and N < 16:
+        return dict(kind="packed", U=2, WPB=WPB)
     ms, nb = _ceil(M, 4), _ceil(N, 16)
     u = 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1
     return dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)
@@ -64,14 +131,15 @@ def generic_variants():
     out = []
     for dt, (_, cplx) in DTYPES.items():
         cw = 2 if cplx else 1
-        # TSMTTSM
-        for mx in ((4, 8) if not cplx else (4,)):
-            out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=mx, maxN=mx,
-                            cfg=dict(kind="valu", MX=mx, NX=mx, U=1, VA=0, VB=0, WPB=WPB)))
-        for mbt, nb in ((1, 1), (1, 2), (2, 1), (2, 2), (1, 4), (4, 1), (2, 4), (4, 2), (4, 4)):
-            mw = 1 if mbt * nb * 4 * cw <= 64 or mbt == 1 else 2
+        # TSMTTSM: row packing up to 16, then blocked matrix-core kernels
+        out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16, maxN=16,
+                        cfg=dict(kind="packed", U=4, WPB=WPB)))
+        for mbt, nb in ((1, 2), (2, 1), (2, 2), (1, 4), (4, 1), (2, 4), (4, 2), (4, 4)):
+            mw = 1
+            while mbt * nb * 4 * cw > 32 * mw and mw < mbt:
+                mw *= 2
             mb = _ceil(mbt, mw)
-            u = max(1, min(4, 16 // ((mb + nb) * cw)))
+            u = max(1, min(4, 8 // ((mb + nb) * cw)))
             out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
                             cfg=dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)))
         # TSMM
@@ -84,6 +152,23 @@ def generic_variants():
                 out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb,
                                 cfg=dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)))
     return out
+
+
+def tuning_variants(widths):
+    """All candidates of every (op, dtype, width) in ``widths``, plus the
+    run-time-width variants (the library the autotuner times)."""
+    out = []
+    seen = set()
+    for op in OPS:
+        for dt in DTYPES:
+            for (M, N) in widths:
+                for c in candidates(op, dt, M, N):
+                    v = dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=c)
+                    name = variant_name(v)
+                    if name not in seen:
+                        seen.add(name)
+                        out.append(v)
+    return out + generic_variants()
 
 
 def load_tuned(path):
@@ -111,10 +196,14 @@ def variant_name(v):
     w = "%dx%d" % (v["M"], v["N"]) if v["M"] else "le%dx%d" % (v["maxM"], v["maxN"])
     if c["kind"] == "valu":
         tag = "valu_u%d" % c["U"]
+    elif c["kind"] == "packed":
+        tag = "packed_u%d" % c["U"]
     elif v["op"] == "tsmttsm":
         tag = "mfma_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
     else:
         tag = "mfma_s%dn%d_u%d" % (c["MS"], c["NB"], c["U"])
+    if c.get("WPB", WPB) != WPB:
+        tag += "_w%d" % c["WPB"]
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -122,6 +211,8 @@ def _template(v):
     c = v["cfg"]
     cplx = "true" if DTYPES[v["dt"]][1] else "false"
     M, N = v["M"], v["N"]
+    if c["kind"] == "packed":
+        return "tsg::%s_packed<%d, %d, %d, %s, %d>" % (v["op"], M, N, c["U"], cplx, c["WPB"])
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
@@ -137,7 +228,10 @@ def _template(v):
 
 
 def rows_per_tile(v):
+    """Rows one block consumes per grid-stride step (for packed kinds: per packed row P = 1)."""
     c = v["cfg"]
+    if c["kind"] == "packed":
+        return (4 if v["op"] == "tsmttsm" else 16) * c["U"] * c["WPB"]
     if v["op"] == "tsmttsm":
         return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])
     return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 16 * c["U"] * c["WPB"]
@@ -147,7 +241,7 @@ def _launcher(v, fn):
     tmpl = _template(v)
     threads = 64 * v["cfg"]["WPB"]
     if v["op"] == "tsmttsm":
-        args = "p.K, p.M, p.N, p.A, p.lda, p.X, p.ldx, static_cast<double*>(p.Y), p.ldy, p.ws, p.cnt, p.conj"
+        args = "p.K, p.M, p.N, p.A, p.lda, p.X, p.ldx, static_cast<double*>(p.Y), p.ldy, p.ws, p.conj"
     else:
         args = ("p.K, p.M, p.N, p.A, p.lda, static_cast<const double*>(p.X), p.ldx, p.Y, p.ldy, "
                 "p.alpha, p.beta, p.conj")
@@ -162,9 +256,10 @@ def _record(v, fn):
     pair_a = int(c["kind"] == "valu" and bool(c.get("VA")))
     pair_x = int(c["kind"] == "valu" and bool(c.get("VB")))
     even = int(v["M"] == 0 and (pair_a or pair_x))
-    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
+    pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)
+    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
             % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
-               64 * c["WPB"], rows_per_tile(v), variant_name(v), fn.replace("launch_", "kernel_"), fn))
+               64 * c["WPB"], rows_per_tile(v), pack, variant_name(v), fn.replace("launch_", "kernel_"), fn))
 
 
 def emit(outdir, variants, per_file=6):

@@ -1,16 +1,15 @@
 // tsg_device.hpp -- device-side building blocks shared by the gfx950 kernels:
-// element types, complex multiply-accumulate, wave reductions and the
-// deterministic two-level grid reduction of the per-block partial C.
+// element types, streaming loads, the leap-frog loop driver and wave sums.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tsg {
 
-constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kGroup = 16;         // blocks folded by one first-level reducer
+constexpr int kWave = 64;  // CDNA wavefront width
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // Interleaved complex double (16 B).
 struct zd {
@@ -18,15 +17,55 @@ struct zd {
 };
 
 // ---------------------------------------------------------------- loads
-// Plain loads through the vector memory path; the streaming operands are read
-// exactly once, so they are marked non-temporal.
+// The tall operands are read exactly once: non-temporal loads.  Callers pass
+// addresses that are always inside the matrix (out-of-range rows and columns
+// are clamped to a valid element and the value is zeroed afterwards), so every
+// load is issued unconditionally and the compiler can count the loads in
+// flight and wait only for the ones it needs.
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 
 __device__ __forceinline__ zd ld_stream(const zd* p)
 {
-    typedef double d2 __attribute__((ext_vector_type(2)));
-    d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p));
     return zd{v.x, v.y};
+}
+
+__device__ __forceinline__ dbl2 ld_stream2(const double* p)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p));
+}
+
+__device__ __forceinline__ double keep(bool ok, double v) { return ok ? v : 0.0; }
+__device__ __forceinline__ zd keep(bool ok, zd v) { return ok ? v : zd{0.0, 0.0}; }
+
+// ------------------------------------------------------- leap-frog driver
+// Grid-stride loop over tiles t = t0, t0 + G, ... < ntiles with two register
+// sets used in turn: the loads of the next tile are issued before the current
+// tile is computed (the paper's leap frogging, Section 3.1), without copying
+// the "next" registers into the "current" ones.
+template <class Buf, class Load, class Compute>
+__device__ __forceinline__ void leapfrog(int64_t t, int64_t ntiles, int64_t G, Buf& x, Buf& y, Load load,
+                                         Compute compute)
+{
+    if (t >= ntiles) return;
+    load(t, x);
+    while (true) {
+        const int64_t t1 = t + G;
+        if (t1 >= ntiles) {
+            compute(t, x);
+            return;
+        }
+        load(t1, y);
+        compute(t, x);
+        const int64_t t2 = t1 + G;
+        if (t2 >= ntiles) {
+            compute(t1, y);
+            return;
+        }
+        load(t2, x);
+        compute(t1, y);
+        t = t2;
+    }
 }
 
 // -------------------------------------------------- wave reduction (fixed tree)
@@ -37,77 +76,25 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// ------------------------------------------------- grid reduction of partials
-// Every block holds its partial C (E doubles) in LDS.  Blocks write it to the
-// workspace, the last block of each group of kGroup blocks folds its group in
-// block order, and the last group folder folds the group sums in group order
-// and writes C.  Each fold runs in a fixed order, so the result is
-// bitwise reproducible.  Counters return to zero after use, so no memset is
-// needed between launches.
-//
-// ws layout (doubles): level-1 partials [G][E], then level-2 partials [NG][E].
-// cnt layout: NG first-level counters, then one second-level counter.
-//
-// `store(e, v)` writes the final value of partial entry e to C.
-template <class Store>
-__device__ void grid_fold(const double* lds_part, int E, double* __restrict__ ws,
-                          unsigned* __restrict__ cnt, Store store)
+// ------------------------------------------------------- block partial out
+// Every block of a TSMTTSM launch ends with its partial C (E doubles) in LDS.
+// A grid of one block writes C directly; otherwise the partial goes to slot
+// blockIdx.x of the workspace and a second kernel (fold_partials) sums the
+// slots in a fixed order.  The kernel boundary orders the two, so no
+// device-scope fence or atomic is needed.
+template <int CW>
+__device__ __forceinline__ void block_out(const double* part, int E, int N, double* __restrict__ ws,
+                                          double* __restrict__ C, int64_t ldc)
 {
-    __shared__ int s_flag;
-    const int G = gridDim.x;
-    const int b = blockIdx.x;
-    const int NG = (G + kGroup - 1) / kGroup;
-    const int grp = b / kGroup;
-    const int grp_size = min(kGroup, G - grp * kGroup);
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-
-    if (G == 1) {
-        for (int e = tid; e < E; e += nt) store(e, lds_part[e]);
-        return;
-    }
-    double* l1 = ws;
-    double* l2 = ws + (size_t)G * E;
-    for (int e = tid; e < E; e += nt) l1[(size_t)b * E + e] = lds_part[e];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        unsigned t = __hip_atomic_fetch_add(&cnt[grp], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag = (t == (unsigned)(grp_size - 1));
-    }
-    __syncthreads();
-    if (!s_flag) return;
-    __threadfence();
-    if (tid == 0) __hip_atomic_store(&cnt[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
-    const double* src = l1 + (size_t)grp * kGroup * E;
-    if (NG == 1) {
-        for (int e = tid; e < E; e += nt) {
-            double s = 0.0;
-            for (int j = 0; j < grp_size; ++j) s += src[(size_t)j * E + e];
-            store(e, s);
+    if (gridDim.x == 1) {
+        for (int e = threadIdx.x; e < E; e += blockDim.x) {
+            const int q = e / CW;
+            const int m = q / N, n = q - m * N;
+            C[((int64_t)m * ldc + n) * CW + (e - q * CW)] = part[e];
         }
-        return;
-    }
-    for (int e = tid; e < E; e += nt) {
-        double s = 0.0;
-        for (int j = 0; j < grp_size; ++j) s += src[(size_t)j * E + e];
-        l2[(size_t)grp * E + e] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        unsigned t = __hip_atomic_fetch_add(&cnt[NG], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_flag = (t == (unsigned)(NG - 1));
-    }
-    __syncthreads();
-    if (!s_flag) return;
-    __threadfence();
-    if (tid == 0) __hip_atomic_store(&cnt[NG], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int e = tid; e < E; e += nt) {
-        double s = 0.0;
-        for (int j = 0; j < NG; ++j) s += l2[(size_t)j * E + e];
-        store(e, s);
+    } else {
+        double* dst = ws + (size_t)blockIdx.x * E;
+        for (int e = threadIdx.x; e < E; e += blockDim.x) dst[e] = part[e];
     }
 }
 

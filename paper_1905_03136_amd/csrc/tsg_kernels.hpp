@@ -1,5 +1,5 @@
 // tsg_kernels.hpp -- gfx950 kernel templates for the two tall & skinny products
-//   TSMTTSM  C = op(A)^T B   (Section 3 of the paper)
+//   TSMTTSM  C = op(A)^T B            (Section 3 of the paper)
 //   TSMM     B = alpha op(A) C + beta B   (Section 4)
 // A (K x M), B (K x N) row-major with leading dimensions lda, ldb; C (M x N)
 // row-major with ldc.  Complex data are interleaved (re, im) doubles.
@@ -24,6 +24,11 @@ __device__ __forceinline__ double zero_of<double>() { return 0.0; }
 template <>
 __device__ __forceinline__ zd zero_of<zd>() { return zd{0.0, 0.0}; }
 
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // ============================================================================
 // TSMTTSM on the matrix cores.
 //
@@ -36,8 +41,8 @@ __device__ __forceinline__ zd zero_of<zd>() { return zd{0.0, 0.0}; }
 // 128-byte (256-byte complex) segment, each element of A and B is read from
 // HBM exactly once, and no lane needs another lane's data.  This is the
 // paper's tiled K-loop mapping (Section 3, Listings 2-5) with the register
-// tile replaced by matrix-core accumulators; the "next" fragment set is
-// loaded while the current one is multiplied (leap frogging, Section 3.1).
+// tile replaced by matrix-core accumulators; the fragments of the next tile
+// are loaded while the current ones are multiplied (leap frogging, Section 3.1).
 //
 // Complex data use four real products per complex block,
 //   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br,
@@ -54,7 +59,7 @@ template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
-             double* __restrict__ ws, unsigned* __restrict__ cnt, int conj)
+             double* __restrict__ ws, int conj)
 {
     using T = elem_t<CPLX>;
     constexpr int CW = CPLX ? 2 : 1;
@@ -100,62 +105,54 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             if constexpr (CPLX) acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
 
-    const int64_t ntiles = (K + RT - 1) / RT;
-    T a[U][MB], b[U][NB], an[U][MB], bn[U][NB];
-
-    auto load = [&](int64_t t, T (&xa)[U][MB], T (&xb)[U][NB]) {
+    struct Frag {
+        T a[U][MB];
+        T b[U][NB];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(rg * U + u) * 4 + lr;
             const bool ok = row < K;
-            const T* ar = A + row * lda;
-            const T* br = B + row * ldb;
+            const int64_t rc = ok ? row : K - 1;
+            const T* ar = A + rc * lda;
+            const T* br = B + rc * ldb;
 #pragma unroll
-            for (int i = 0; i < MB; ++i) xa[u][i] = (ok && mok[i]) ? ld_stream(ar + moff[i]) : zero_of<T>();
+            for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok && mok[i], ld_stream(ar + moff[i]));
 #pragma unroll
-            for (int j = 0; j < NB; ++j) xb[u][j] = (ok && nok[j]) ? ld_stream(br + noff[j]) : zero_of<T>();
+            for (int j = 0; j < NB; ++j) f.b[u][j] = keep(ok && nok[j], ld_stream(br + noff[j]));
         }
     };
-
-    int64_t t = blockIdx.x;
-    if (t < ntiles) load(t, a, b);
-    for (; t < ntiles; t += gridDim.x) {
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) load(tn, an, bn);
+    auto compute = [&](int64_t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if constexpr (!CPLX) {
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int j = 0; j < NB; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][i], b[u][j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i], f.b[u][j], acc[i][j]);
             } else {
                 double nbi[NB];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) nbi[j] = -b[u][j].im;
+                for (int j = 0; j < NB; ++j) nbi[j] = -f.b[u][j].im;
 #pragma unroll
                 for (int i = 0; i < MB; ++i) {
-                    const double ar = a[u][i].re;
-                    const double ai = conj ? -a[u][i].im : a[u][i].im;
+                    const double ar = f.a[u][i].re;
+                    const double ai = conj ? -f.a[u][i].im : f.a[u][i].im;
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b[u][j].re, acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, nbi[j], acc[i][j], 0, 0, 0);
-                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b[u][j].im, acci[i][j], 0, 0, 0);
-                        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b[u][j].re, acci[i][j], 0, 0, 0);
+                        acc[i][j] = mfma16(ar, f.b[u][j].re, acc[i][j]);
+                        acc[i][j] = mfma16(ai, nbi[j], acc[i][j]);
+                        acci[i][j] = mfma16(ar, f.b[u][j].im, acci[i][j]);
+                        acci[i][j] = mfma16(ai, f.b[u][j].re, acci[i][j]);
                     }
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int i = 0; i < MB; ++i) a[u][i] = an[u][i];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) b[u][j] = bn[u][j];
-        }
-    }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
 
     // Fold the row groups into the block partial, one group after the other.
     const int E = M * N * CW;
@@ -178,11 +175,109 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
         }
         __syncthreads();
     }
-    grid_fold(part, E, ws, cnt, [&](int e, double v) {
-        const int q = e / CW;
-        const int m = q / N, n = q - (q / N) * N;
-        C[((int64_t)m * ldc + n) * CW + (e - q * CW)] = v;
-    });
+    block_out<CW>(part, E, N, ws, C, ldc);
+}
+
+// ============================================================================
+// TSMTTSM on the matrix cores for narrow widths (M, N <= 16): row packing.
+//
+// With M, N < 16 a plain 16 x 16 fragment would leave most lanes idle and
+// make every load strided.  Instead, P = min(16 / M, 16 / N) consecutive rows
+// are packed into one fragment: lane i (0..15) of k-slot q holds
+// A(k0 + q P + i / M, i % M) and B(k0 + q P + i / N, i % N).  With lda = M the
+// sixteen lanes of a slot read 16 consecutive elements, i.e. the wave reads
+// 4 P complete rows as one contiguous run.  Of the 16 x 16 product only the
+// entries whose row and column come from the same packed row (i / M == j / N)
+// are partial sums of C; the others are discarded.  The packed blocks are
+// summed in a fixed order in the epilogue.  The matrix cores have ample
+// throughput for the low arithmetic intensity of these widths (Eq. 1: M/8
+// flop per byte), so the unused products cost no time.
+// ============================================================================
+template <int MC, int NC, int U, bool CPLX, int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+               const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
+               double* __restrict__ ws, int conj)
+{
+    using T = elem_t<CPLX>;
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int MX = MC ? MC : 16;
+    constexpr int NX = NC ? NC : 16;
+    static_assert(MX <= 16 && NX <= 16, "row packing serves widths up to 16");
+    const int M = MC ? MC : Mr;
+    const int N = NC ? NC : Nr;
+    const int P = MC && NC ? (16 / (MC > NC ? MC : NC)) : 16 / (M > N ? M : N);
+    const int RS = 4 * P;          // rows per MFMA step of one wave
+    const int64_t RT = (int64_t)RS * U * WPB;
+    __shared__ double part[WPB * 16 * 16 * CW];
+    __shared__ double fin[MX * NX * CW];
+
+    const T* __restrict__ A = static_cast<const T*>(Av);
+    const T* __restrict__ B = static_cast<const T*>(Bv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int q = lane >> 4;
+    const int i = lane & 15;
+    const int ha = i / M, ca = i - ha * M;
+    const int hb = i / N, cb = i - hb * N;
+    const bool aok = ha < P, bok = hb < P;
+
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+    dbl4 acci = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    struct Frag {
+        T a[U];
+        T b[U];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r0 = t * RT + (int64_t)(wave * U + u) * RS + q * P;
+            const int64_t ra = r0 + (aok ? ha : 0), rb = r0 + (bok ? hb : 0);
+            const bool oka = aok && ra < K, okb = bok && rb < K;
+            f.a[u] = keep(oka, ld_stream(A + (oka ? ra : K - 1) * lda + (aok ? ca : 0)));
+            f.b[u] = keep(okb, ld_stream(B + (okb ? rb : K - 1) * ldb + (bok ? cb : 0)));
+        }
+    };
+    auto compute = [&](int64_t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (!CPLX) {
+                acc = mfma16(f.a[u], f.b[u], acc);
+            } else {
+                const double ai = conj ? -f.a[u].im : f.a[u].im;
+                acc = mfma16(f.a[u].re, f.b[u].re, acc);
+                acc = mfma16(ai, -f.b[u].im, acc);
+                acci = mfma16(f.a[u].re, f.b[u].im, acci);
+                acci = mfma16(ai, f.b[u].re, acci);
+            }
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, (int64_t)gridDim.x, x, y, load, compute);
+
+    // D(i, j) with i = lane / 16 + 4 r, j = lane % 16 -> LDS, then the diagonal
+    // blocks (i / M == j / N) are summed over packed rows and waves in order.
+    double* mine = part + wave * 256 * CW;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = ((lane >> 4) + 4 * r) * 16 + (lane & 15);
+        mine[e * CW] = acc[r];
+        if constexpr (CPLX) mine[e * CW + 1] = acci[r];
+    }
+    __syncthreads();
+    const int E = M * N * CW;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int qq = e / CW, c = e - qq * CW;
+        const int m = qq / N, n = qq - m * N;
+        double s = 0.0;
+        for (int w = 0; w < WPB; ++w)
+            for (int h = 0; h < P; ++h) s += part[(w * 256 + (h * M + m) * 16 + (h * N + n)) * CW + c];
+        fin[e] = s;
+    }
+    __syncthreads();
+    block_out<CW>(fin, E, N, ws, C, ldc);
 }
 
 // ============================================================================
@@ -191,22 +286,22 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // Parallelisation over K only (the paper's Fig. "genv1" mapping): every lane
 // owns whole rows and keeps the full M x N partial C in registers, so a lane
 // needs no data of any other lane and each FMA operand is a register.  A wave
-// covers 64 consecutive rows per load instruction.  U rows per lane are in
-// flight per iteration and the next iteration's rows are loaded while the
-// current ones are multiplied (leap frogging).  After the K loop the lanes'
-// partials are summed by a fixed butterfly (wave_sum), the waves of a block
-// one after the other, and the blocks by grid_fold.
+// covers 64 consecutive rows per load instruction; U rows per lane are in
+// flight per tile and the next tile is loaded while the current one is
+// multiplied (leap frogging).  After the K loop the lanes' partials are summed
+// by a fixed butterfly (wave_sum) and the waves of a block one after the
+// other.
 //
 // MX x NX bound the register tile; MC / NC = 0 takes M, N at run time
-// (entries beyond them are skipped by guards).  VA / VB load pairs of doubles
-// with one 16-byte load (needs even widths, even leading dimensions and
-// 16-byte aligned pointers; real data only).
+// (entries beyond them are zero).  VA / VB load pairs of doubles with one
+// 16-byte load (needs even widths, even leading dimensions and 16-byte
+// aligned pointers; real data only).
 // ============================================================================
 template <int MC, int NC, int MX, int NX, int U, bool CPLX, bool VA, bool VB, int WPB>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
-             double* __restrict__ ws, unsigned* __restrict__ cnt, int conj)
+             double* __restrict__ ws, int conj)
 {
     using T = elem_t<CPLX>;
     constexpr int CW = CPLX ? 2 : 1;
@@ -230,50 +325,50 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
         for (int j = 0; j < NX; ++j) acc[i][j] = zero_of<T>();
 
-    const int64_t ntiles = (K + RT - 1) / RT;
-    T a[U][MX], b[U][NX], an[U][MX], bn[U][NX];
-
-    auto load = [&](int64_t t, T (&xa)[U][MX], T (&xb)[U][NX]) {
+    struct Frag {
+        T a[U][MX];
+        T b[U][NX];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * kWave + lane;
             const bool ok = row < K;
-            const T* ar = A + row * lda;
-            const T* br = B + row * ldb;
+            const int64_t rc = ok ? row : K - 1;
+            const T* ar = A + rc * lda;
+            const T* br = B + rc * ldb;
             if constexpr (VA) {
-                typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
                 for (int i = 0; i < MX; i += 2) {
-                    d2 v = d2{0.0, 0.0};
-                    if (ok && (MC || i < M)) v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(ar + i));
-                    xa[u][i] = v.x;
-                    xa[u][i + 1] = v.y;
+                    const dbl2 v = ld_stream2(ar + i);
+                    f.a[u][i] = keep(ok, v.x);
+                    f.a[u][i + 1] = keep(ok, v.y);
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < MX; ++i) xa[u][i] = (ok && (MC || i < M)) ? ld_stream(ar + i) : zero_of<T>();
+                for (int i = 0; i < MX; ++i) {
+                    const bool in = MC || i < M;
+                    f.a[u][i] = keep(ok && in, ld_stream(ar + (in ? i : 0)));
+                }
             }
             if constexpr (VB) {
-                typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
                 for (int j = 0; j < NX; j += 2) {
-                    d2 v = d2{0.0, 0.0};
-                    if (ok && (NC || j < N)) v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(br + j));
-                    xb[u][j] = v.x;
-                    xb[u][j + 1] = v.y;
+                    const dbl2 v = ld_stream2(br + j);
+                    f.b[u][j] = keep(ok, v.x);
+                    f.b[u][j + 1] = keep(ok, v.y);
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < NX; ++j) xb[u][j] = (ok && (NC || j < N)) ? ld_stream(br + j) : zero_of<T>();
+                for (int j = 0; j < NX; ++j) {
+                    const bool in = NC || j < N;
+                    f.b[u][j] = keep(ok && in, ld_stream(br + (in ? j : 0)));
+                }
             }
         }
     };
-
-    int64_t t = blockIdx.x;
-    if (t < ntiles) load(t, a, b);
-    for (; t < ntiles; t += gridDim.x) {
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) load(tn, an, bn);
+    auto compute = [&](int64_t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -281,23 +376,18 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
                 for (int j = 0; j < NX; ++j) {
                     if constexpr (!CPLX) {
-                        acc[i][j] = __builtin_fma(a[u][i], b[u][j], acc[i][j]);
+                        acc[i][j] = __builtin_fma(f.a[u][i], f.b[u][j], acc[i][j]);
                     } else {
-                        const double ai = conj ? -a[u][i].im : a[u][i].im;
-                        acc[i][j].re = __builtin_fma(a[u][i].re, b[u][j].re, acc[i][j].re);
-                        acc[i][j].re = __builtin_fma(-ai, b[u][j].im, acc[i][j].re);
-                        acc[i][j].im = __builtin_fma(a[u][i].re, b[u][j].im, acc[i][j].im);
-                        acc[i][j].im = __builtin_fma(ai, b[u][j].re, acc[i][j].im);
+                        const double ai = conj ? -f.a[u][i].im : f.a[u][i].im;
+                        acc[i][j].re = __builtin_fma(f.a[u][i].re, f.b[u][j].re, acc[i][j].re);
+                        acc[i][j].re = __builtin_fma(-ai, f.b[u][j].im, acc[i][j].re);
+                        acc[i][j].im = __builtin_fma(f.a[u][i].re, f.b[u][j].im, acc[i][j].im);
+                        acc[i][j].im = __builtin_fma(ai, f.b[u][j].re, acc[i][j].im);
                     }
                 }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int i = 0; i < MX; ++i) a[u][i] = an[u][i];
-#pragma unroll
-            for (int j = 0; j < NX; ++j) b[u][j] = bn[u][j];
-        }
-    }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
 
     // Wave sums (fixed butterfly), then the waves folded one after the other.
     const int E = M * N * CW;
@@ -333,11 +423,7 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
         }
         __syncthreads();
     }
-    grid_fold(part, E, ws, cnt, [&](int e, double v) {
-        const int q = e / CW;
-        const int m = q / N, n = q - (q / N) * N;
-        C[((int64_t)m * ldc + n) * CW + (e - q * CW)] = v;
-    });
+    block_out<CW>(part, E, N, ws, C, ldc);
 }
 
 // ============================================================================
@@ -346,9 +432,10 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // Parallelisation over K only (the paper's Fig. "tsmm_mapping_1T" mapping):
 // a lane computes whole rows of B.  All lanes of a wave use the same entry of
 // C at the same time, so C is read through the scalar unit into SGPRs and
-// broadcast to the FMAs: no LDS traffic and no per-lane C registers.  The
-// rows of a wave are consecutive, so the wave's stores fill whole cache lines
-// in L2 before they are written back (no write-allocate traffic on CDNA).
+// broadcast to the FMAs: no LDS traffic and no per-lane copy of C.  The rows
+// of a wave are consecutive, so the wave's stores fill whole cache lines in
+// L2 before they are written back (no write-allocate traffic on CDNA).
+// Full tiles store without guards; only the last, ragged tile is guarded.
 // ============================================================================
 template <int MC, int NC, int MX, int NX, int U, bool CPLX, bool VA, bool VB, int WPB>
 __global__ void __launch_bounds__(WPB * kWave)
@@ -367,102 +454,98 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const bool read_b = beta != 0.0;
-    const int64_t ntiles = (K + RT - 1) / RT;
 
-    T a[U][MX], an[U][MX];
-    auto load = [&](int64_t t, T (&xa)[U][MX]) {
+    struct Frag {
+        T a[U][MX];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * kWave + lane;
-            const bool ok = row < K;
-            const T* ar = A + row * lda;
+            const int64_t rc = row < K ? row : K - 1;
+            const T* ar = A + rc * lda;
             if constexpr (VA) {
-                typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
                 for (int i = 0; i < MX; i += 2) {
-                    d2 v = d2{0.0, 0.0};
-                    if (ok && (MC || i < M)) v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(ar + i));
-                    xa[u][i] = v.x;
-                    xa[u][i + 1] = v.y;
+                    const dbl2 v = ld_stream2(ar + i);
+                    f.a[u][i] = v.x;
+                    f.a[u][i + 1] = v.y;
                 }
             } else {
 #pragma unroll
-                for (int i = 0; i < MX; ++i) xa[u][i] = (ok && (MC || i < M)) ? ld_stream(ar + i) : zero_of<T>();
+                for (int i = 0; i < MX; ++i) {
+                    const bool in = MC || i < M;
+                    f.a[u][i] = keep(in, ld_stream(ar + (in ? i : 0)));
+                }
             }
         }
     };
-
-    int64_t t = blockIdx.x;
-    if (t < ntiles) load(t, a);
-    for (; t < ntiles; t += gridDim.x) {
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) load(tn, an);
+    auto row_out = [&](const T (&a)[MX], T (&out)[NX]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t row = t * RT + (int64_t)(wave * U + u) * kWave + lane;
-            if (row < K) {
-                T* br = B + row * ldb;
-                T out[NX];
+        for (int j = 0; j < NX; ++j) {
+            T s = zero_of<T>();
 #pragma unroll
-                for (int j = 0; j < NX; ++j) {
-                    T s = zero_of<T>();
-#pragma unroll
-                    for (int i = 0; i < MX; ++i) {
-                        if ((MC || i < M) && (NC || j < N)) {
-                            const T c = Cz[(int64_t)i * ldc + j];
-                            if constexpr (!CPLX) {
-                                s = __builtin_fma(a[u][i], c, s);
-                            } else {
-                                const double ai = conj ? -a[u][i].im : a[u][i].im;
-                                s.re = __builtin_fma(a[u][i].re, c.re, s.re);
-                                s.re = __builtin_fma(-ai, c.im, s.re);
-                                s.im = __builtin_fma(a[u][i].re, c.im, s.im);
-                                s.im = __builtin_fma(ai, c.re, s.im);
-                            }
-                        }
+            for (int i = 0; i < MX; ++i) {
+                if ((MC || i < M) && (NC || j < N)) {
+                    const T c = Cz[(int64_t)i * ldc + j];
+                    if constexpr (!CPLX) {
+                        s = __builtin_fma(a[i], c, s);
+                    } else {
+                        const double ai = conj ? -a[i].im : a[i].im;
+                        s.re = __builtin_fma(a[i].re, c.re, s.re);
+                        s.re = __builtin_fma(-ai, c.im, s.re);
+                        s.im = __builtin_fma(a[i].re, c.im, s.im);
+                        s.im = __builtin_fma(ai, c.re, s.im);
                     }
-                    out[j] = s;
                 }
-                if constexpr (VB) {
-                    typedef double d2 __attribute__((ext_vector_type(2)));
+            }
+            out[j] = s;
+        }
+    };
+    auto store_row = [&](T* br, const T (&out)[NX]) {
+        if constexpr (VB) {
 #pragma unroll
-                    for (int j = 0; j < NX; j += 2) {
-                        if (NC || j < N) {
-                            d2 v = d2{alpha * out[j], alpha * out[j + 1]};
-                            if (read_b) {
-                                const d2 o = *reinterpret_cast<const d2*>(br + j);
-                                v = d2{__builtin_fma(beta, o.x, v.x), __builtin_fma(beta, o.y, v.y)};
-                            }
-                            __builtin_nontemporal_store(v, reinterpret_cast<d2*>(br + j));
-                        }
-                    }
-                } else {
+            for (int j = 0; j < NX; j += 2) {
+                dbl2 v = dbl2{alpha * out[j], alpha * out[j + 1]};
+                if (read_b) {
+                    const dbl2 o = *reinterpret_cast<const dbl2*>(br + j);
+                    v = dbl2{__builtin_fma(beta, o.x, v.x), __builtin_fma(beta, o.y, v.y)};
+                }
+                __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(br + j));
+            }
+        } else {
 #pragma unroll
-                    for (int j = 0; j < NX; ++j) {
-                        if (NC || j < N) {
-                            if constexpr (!CPLX) {
-                                double v = alpha * out[j];
-                                if (read_b) v = __builtin_fma(beta, br[j], v);
-                                __builtin_nontemporal_store(v, br + j);
-                            } else {
-                                typedef double d2 __attribute__((ext_vector_type(2)));
-                                d2 v = d2{alpha * out[j].re, alpha * out[j].im};
-                                if (read_b) {
-                                    const zd o = br[j];
-                                    v = d2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
-                                }
-                                __builtin_nontemporal_store(v, reinterpret_cast<d2*>(br + j));
-                            }
+            for (int j = 0; j < NX; ++j) {
+                if (NC || j < N) {
+                    if constexpr (!CPLX) {
+                        double v = alpha * out[j];
+                        if (read_b) v = __builtin_fma(beta, br[j], v);
+                        __builtin_nontemporal_store(v, br + j);
+                    } else {
+                        dbl2 v = dbl2{alpha * out[j].re, alpha * out[j].im};
+                        if (read_b) {
+                            const zd o = br[j];
+                            v = dbl2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
                         }
+                        __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(br + j));
                     }
                 }
             }
         }
+    };
+    auto compute = [&](int64_t t, Frag& f) {
+        const bool full = (t + 1) * RT <= K;
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int i = 0; i < MX; ++i) a[u][i] = an[u][i];
-    }
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = t * RT + (int64_t)(wave * U + u) * kWave + lane;
+            T out[NX];
+            row_out(f.a[u], out);
+            if (full || row < K) store_row(B + row * ldb, out);
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
 }
 
 // ============================================================================
@@ -526,27 +609,24 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         koff[s] = kok[s] ? m : 0;
     }
 
-    const int64_t ntiles = (K + RT - 1) / RT;
-    T a[U][MS], an[U][MS];
-    auto load = [&](int64_t t, T (&xa)[U][MS]) {
+    struct Frag {
+        T a[U][MS];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lc;
-            const bool ok = row < K;
-            const T* ar = A + row * lda;
+            const int64_t rc = row < K ? row : K - 1;
+            const T* ar = A + rc * lda;
 #pragma unroll
-            for (int s = 0; s < MS; ++s) xa[u][s] = (ok && kok[s]) ? ld_stream(ar + koff[s]) : zero_of<T>();
+            for (int s = 0; s < MS; ++s) f.a[u][s] = keep(kok[s], ld_stream(ar + koff[s]));
         }
     };
-
-    int64_t t = blockIdx.x;
-    if (t < ntiles) load(t, a);
-    for (; t < ntiles; t += gridDim.x) {
+    auto compute = [&](int64_t t, Frag& f) {
         // Compiler-only barrier: keeps the loop-invariant C operands in LDS
         // instead of letting them be hoisted into (too many) registers.
         __asm__ volatile("" ::: "memory");
-        const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) load(tn, an);
         dbl4 acc[U][NB];
         dbl4 acci[CPLX ? U : 1][CPLX ? NB : 1];
 #pragma unroll
@@ -563,57 +643,202 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 const double cr = cf[(s * NB + j) * kWave + lane];
                 if constexpr (!CPLX) {
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        acc[u][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], cr, acc[u][j], 0, 0, 0);
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s], cr, acc[u][j]);
                 } else {
                     const double ci = cf[NFRAG + (s * NB + j) * kWave + lane];
                     const double nci = -ci;
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const double ar = a[u][s].re;
-                        const double ai = conj ? -a[u][s].im : a[u][s].im;
-                        acc[u][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, cr, acc[u][j], 0, 0, 0);
-                        acc[u][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, nci, acc[u][j], 0, 0, 0);
-                        acci[u][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ci, acci[u][j], 0, 0, 0);
-                        acci[u][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, cr, acci[u][j], 0, 0, 0);
+                        const double ar = f.a[u][s].re;
+                        const double ai = conj ? -f.a[u][s].im : f.a[u][s].im;
+                        acc[u][j] = mfma16(ar, cr, acc[u][j]);
+                        acc[u][j] = mfma16(ai, nci, acc[u][j]);
+                        acci[u][j] = mfma16(ar, ci, acci[u][j]);
+                        acci[u][j] = mfma16(ai, cr, acci[u][j]);
                     }
                 }
             }
+        const bool full = (t + 1) * RT <= K;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t rbase = t * RT + (int64_t)(wave * U + u) * 16 + lr;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int n = 16 * j + lc;
-                if (n < N) {
+                if ((NC && (NC % 16 == 0)) || n < N) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t row = rbase + 4 * r;
-                        if (row < K) {
+                        if (full || row < K) {
                             T* p = B + row * ldb + n;
                             if constexpr (!CPLX) {
                                 double v = alpha * acc[u][j][r];
                                 if (read_b) v = __builtin_fma(beta, *p, v);
                                 __builtin_nontemporal_store(v, p);
                             } else {
-                                typedef double d2 __attribute__((ext_vector_type(2)));
-                                d2 v = d2{alpha * acc[u][j][r], alpha * acci[u][j][r]};
+                                dbl2 v = dbl2{alpha * acc[u][j][r], alpha * acci[u][j][r]};
                                 if (read_b) {
                                     const zd o = *p;
-                                    v = d2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
+                                    v = dbl2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
                                 }
-                                __builtin_nontemporal_store(v, reinterpret_cast<d2*>(p));
+                                __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p));
                             }
                         }
                     }
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int s = 0; s < MS; ++s) a[u][s] = an[u][s];
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
+}
+
+// ============================================================================
+// TSMM on the matrix cores for narrow widths (N <= 16): row packing.
+//
+// P = 16 / N rows of B are packed into the 16 columns of one output fragment:
+// output column j = h N + n (h < P) of fragment row i is B(k0 + i P + h, n),
+// so with ldb = N a lane's four outputs and the wave's 16 x 16 fragment are
+// 512 contiguous bytes of B.  The contraction index runs over the pairs
+// q = h M + m (h < P, m < M) in steps of four; the C operand of pair q and
+// column j is C(m, n) when both belong to the same packed row h and zero
+// otherwise (a block-diagonal copy of C, staged once per block in LDS in
+// fragment order).  A lane's A operand for pair q is A(k0 + i P + h, m).
+// ============================================================================
+template <int MC, int NC, int U, bool CPLX, int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+            const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
+            double alpha, double beta, int conj)
+{
+    static_assert(MC > 0 && NC > 0 && NC <= 16, "row-packed TSMM needs compile-time widths, N <= 16");
+    using T = elem_t<CPLX>;
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int P = 16 / NC;
+    constexpr int QN = P * MC;             // contraction pairs (h, m)
+    constexpr int S = (QN + 3) / 4;        // MFMA steps per fragment
+    constexpr int RS = 16 * P;             // rows per fragment
+    constexpr int RT = RS * U * WPB;       // rows per tile
+    constexpr int NFRAG = S * kWave;
+    __shared__ double cf[NFRAG * CW];
+
+    const T* __restrict__ A = static_cast<const T*>(Av);
+    T* __restrict__ B = static_cast<T*>(Bv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+    const bool read_b = beta != 0.0;
+
+    // C operand fragments: cf[s * 64 + l] = Cop(4s + l/16, l%16).
+    for (int idx = threadIdx.x; idx < NFRAG; idx += blockDim.x) {
+        const int l = idx & (kWave - 1);
+        const int qq = 4 * (idx / kWave) + (l >> 4);
+        const int j = l & 15;
+        const int hq = qq / MC, m = qq - hq * MC;
+        const int hj = j / NC, n = j - hj * NC;
+        const bool ok = qq < QN && hj < P && hq == hj;
+        if constexpr (CPLX) {
+            cf[idx] = ok ? Cm[2 * ((int64_t)m * ldc + n)] : 0.0;
+            cf[NFRAG + idx] = ok ? Cm[2 * ((int64_t)m * ldc + n) + 1] : 0.0;
+        } else {
+            cf[idx] = ok ? Cm[(int64_t)m * ldc + n] : 0.0;
+        }
     }
+    __syncthreads();
+
+    // A operand of step s for this lane: row offset i P + h, column m.
+    int aoff[S];
+    bool aok[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int qq = 4 * s + lr;
+        const int hq = qq / MC, m = qq - hq * MC;
+        aok[s] = qq < QN;
+        aoff[s] = aok[s] ? hq : 0;  // packed row h
+        (void)m;
+    }
+    int acol[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int qq = 4 * s + lr;
+        acol[s] = aok[s] ? qq - (qq / MC) * MC : 0;
+    }
+    const int hj = lc / NC, nj = lc - hj * NC;
+    const bool jok = hj < P;
+
+    struct Frag {
+        T a[U][S];
+    };
+    Frag x, y;
+    auto load = [&](int64_t t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r0 = t * RT + (int64_t)(wave * U + u) * RS + (int64_t)lc * P;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int64_t row = r0 + aoff[s];
+                const bool ok = aok[s] && row < K;
+                f.a[u][s] = keep(ok, ld_stream(A + (ok ? row : K - 1) * lda + acol[s]));
+            }
+        }
+    };
+    auto compute = [&](int64_t t, Frag& f) {
+        __asm__ volatile("" ::: "memory");
+        dbl4 acc[U], acci[CPLX ? U : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (CPLX) acci[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double cr = cf[s * kWave + lane];
+            if constexpr (!CPLX) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[u] = mfma16(f.a[u][s], cr, acc[u]);
+            } else {
+                const double ci = cf[NFRAG + s * kWave + lane];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double ar = f.a[u][s].re;
+                    const double ai = conj ? -f.a[u][s].im : f.a[u][s].im;
+                    acc[u] = mfma16(ar, cr, acc[u]);
+                    acc[u] = mfma16(ai, -ci, acc[u]);
+                    acci[u] = mfma16(ar, ci, acci[u]);
+                    acci[u] = mfma16(ai, cr, acci[u]);
+                }
+            }
+        }
+        const bool full = (t + 1) * (int64_t)RT <= K;
+        if (jok) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t r0 = t * RT + (int64_t)(wave * U + u) * RS + hj;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = r0 + (int64_t)(lr + 4 * r) * P;
+                    if (full || row < K) {
+                        T* p = B + row * ldb + nj;
+                        if constexpr (!CPLX) {
+                            double v = alpha * acc[u][r];
+                            if (read_b) v = __builtin_fma(beta, *p, v);
+                            __builtin_nontemporal_store(v, p);
+                        } else {
+                            dbl2 v = dbl2{alpha * acc[u][r], alpha * acci[u][r]};
+                            if (read_b) {
+                                const zd o = *p;
+                                v = dbl2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
+                            }
+                            __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p));
+                        }
+                    }
+                }
+            }
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, (int64_t)gridDim.x, x, y, load, compute);
 }
 
 }  // namespace tsg

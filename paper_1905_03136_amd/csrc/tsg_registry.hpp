@@ -22,8 +22,7 @@ struct Launch {
     void* Y;
     int64_t ldy;
     double alpha, beta;
-    double* ws;
-    unsigned* cnt;
+    double* ws;  // TSMTTSM: one slot of M*N (x2 complex) doubles per block
 };
 
 enum OpKind { OP_TSMTTSM = 0, OP_TSMM = 1 };
@@ -37,7 +36,8 @@ struct Variant {
     int pairX;          // TSMTTSM: paired loads of B; TSMM: paired stores of B
     int evenW;          // run-time-width variant that needs even widths (paired access)
     int threads;        // block size
-    int rows_per_tile;  // rows consumed by one block per grid-stride iteration
+    int rows_per_tile;  // rows consumed by one block per grid-stride iteration (for P = 1)
+    int pack;           // row packing: 0 none, 1 P = 16 / max(M, N) (TSMTTSM), 2 P = 16 / N (TSMM)
     const char* name;
     const void* (*kernel)(); // device function, for occupancy queries
     void (*launch)(const Launch&);

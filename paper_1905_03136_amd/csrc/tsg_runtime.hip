@@ -16,9 +16,44 @@
 #include "../../include/tsgemm.h"
 #include "tsg_registry.hpp"
 
+namespace tsg {
+
+// Sum of the G per-block partials of a TSMTTSM launch (slot b holds E doubles
+// at ws + b * E) into C, in a fixed order: each block takes EB consecutive
+// entries (EB a power of two <= 64) and 256 / EB slices; slice s sums slots
+// s, s + S, s + 2S, ... in increasing order, and the slices are combined by a
+// fixed pairwise tree.  The result is bitwise reproducible for a given grid.
+template <int CW>
+__global__ void __launch_bounds__(256)
+fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double* __restrict__ C, int64_t ldc)
+{
+    __shared__ double red[256];
+    const int S = 256 / EB;
+    const int el = threadIdx.x & (EB - 1);
+    const int s = threadIdx.x / EB;
+    const int e = blockIdx.x * EB + el;
+    double v = 0.0;
+    if (e < E)
+        for (int b = s; b < G; b += S) v += ws[(size_t)b * E + e];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = S / 2; h >= 1; h >>= 1) {
+        if (s < h) red[threadIdx.x] += red[threadIdx.x + h * EB];
+        __syncthreads();
+    }
+    if (s == 0 && e < E) {
+        const int q = e / CW;
+        const int m = q / N, n = q - m * N;
+        C[((int64_t)m * ldc + n) * CW + (e - q * CW)] = red[el];
+    }
+}
+
+}  // namespace tsg
+
 namespace {
 
 thread_local std::string g_err;
+thread_local std::string g_force;  // variant forced by tsg_force_variant ("" = automatic choice)
 
 tsg_status fail(tsg_status s, const char* fmt, ...)
 {
@@ -32,8 +67,6 @@ tsg_status fail(tsg_status s, const char* fmt, ...)
 }
 
 constexpr int kMaxWidth = 64;
-constexpr int kGroup = 16;          // must equal tsg::kGroup in tsg_device.hpp
-constexpr int kCounterSlots = 4096; // first-level counters + one second-level counter
 
 struct DeviceInfo {
     int cus = 0;
@@ -43,7 +76,6 @@ struct DeviceInfo {
 struct Workspace {
     void* data = nullptr;
     size_t bytes = 0;
-    unsigned* counters = nullptr;
 };
 
 std::mutex g_mu;
@@ -110,6 +142,16 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
     const bool a_pairs = (lda % 2 == 0) && aligned(A, 16);
     const bool x_pairs = (ldx % 2 == 0) && aligned(X, 16);
     const tsg::Variant* best = nullptr;
+    if (!g_force.empty()) {
+        for (int i = 0; i < tsg::kNumVariants; ++i) {
+            const tsg::Variant& v = tsg::kVariants[i];
+            if (g_force != v.name) continue;
+            const bool serves = (v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN);
+            if (v.op == op && v.dt == (int)dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs))
+                return &v;
+        }
+        return nullptr;
+    }
     for (int i = 0; i < tsg::kNumVariants; ++i) {
         const tsg::Variant& v = tsg::kVariants[i];
         if (v.op != op || v.dt != (int)dt) continue;
@@ -129,7 +171,7 @@ tsg_status get_workspace(int dev, hipStream_t stream, size_t bytes, Workspace** 
     if (lim && bytes > (size_t)strtoull(lim, nullptr, 10))
         return fail(TSG_E_NOMEM, "workspace of %zu bytes exceeds TSG_MAX_WORKSPACE=%s", bytes, lim);
     Workspace& w = g_ws[std::make_pair(dev, stream)];
-    if (w.counters && w.bytes >= bytes) {
+    if (w.data && w.bytes >= bytes) {
         *out = &w;
         return TSG_OK;
     }
@@ -138,25 +180,17 @@ tsg_status get_workspace(int dev, hipStream_t stream, size_t bytes, Workspace** 
         return fail(TSG_E_CAPTURE, "workspace must grow to %zu bytes while the stream is captured; "
                                    "run the call once before capture or use tsg_reserve", bytes);
     hipError_t e;
-    if (!w.counters) {
-        e = hipMalloc(reinterpret_cast<void**>(&w.counters), kCounterSlots * sizeof(unsigned));
-        if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(counters): %s", hipGetErrorString(e));
-        e = hipMemset(w.counters, 0, kCounterSlots * sizeof(unsigned));
-        if (e != hipSuccess) return fail(TSG_E_HIP, "hipMemset(counters): %s", hipGetErrorString(e));
+    if (w.data) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail(TSG_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        hipFree(w.data);
+        w.data = nullptr;
+        w.bytes = 0;
     }
-    if (w.bytes < bytes) {
-        if (w.data) {
-            e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return fail(TSG_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-            hipFree(w.data);
-            w.data = nullptr;
-            w.bytes = 0;
-        }
-        size_t grow = bytes < (1u << 20) ? (1u << 20) : bytes;
-        e = hipMalloc(&w.data, grow);
-        if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(%zu): %s", grow, hipGetErrorString(e));
-        w.bytes = grow;
-    }
+    size_t grow = bytes < (1u << 20) ? (1u << 20) : bytes;
+    e = hipMalloc(&w.data, grow);
+    if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+    w.bytes = grow;
     *out = &w;
     return TSG_OK;
 }
@@ -196,9 +230,12 @@ tsg_status validate(tsg_dtype dt, int64_t K, int32_t M, int32_t N, const void* A
     return TSG_OK;
 }
 
-int grid_for(int dev, const tsg::Variant& v, int64_t K, int cus)
+int grid_for(int dev, const tsg::Variant& v, int64_t K, int M, int N, int cus)
 {
-    const int64_t tiles = (K + v.rows_per_tile - 1) / v.rows_per_tile;
+    int64_t rows = v.rows_per_tile;
+    if (v.pack == 1) rows *= 16 / (M > N ? M : N);
+    if (v.pack == 2) rows *= 16 / N;
+    const int64_t tiles = (K + rows - 1) / rows;
     const int64_t cap = (int64_t)cus * occupancy(dev, v);
     int64_t g = tiles < cap ? tiles : cap;
     return g < 1 ? 1 : (int)g;
@@ -207,8 +244,23 @@ int grid_for(int dev, const tsg::Variant& v, int64_t K, int cus)
 size_t tsmttsm_ws_bytes(int grid, int M, int N, bool cplx)
 {
     const size_t E = (size_t)M * N * (cplx ? 2 : 1);
-    const size_t ng = (grid + kGroup - 1) / kGroup;
-    return grid > 1 ? (grid + ng) * E * sizeof(double) : 0;
+    return grid > 1 ? (size_t)grid * E * sizeof(double) : 0;
+}
+
+// Launch the fold of the per-block partials (grid > 1) into C.
+hipError_t launch_fold(const tsg::Launch& p, bool cplx)
+{
+    const int E = p.M * p.N * (cplx ? 2 : 1);
+    int eb = 1;
+    while (eb < E && eb < 64) eb <<= 1;
+    const int blocks = (E + eb - 1) / eb;
+    if (cplx)
+        hipLaunchKernelGGL((tsg::fold_partials<2>), dim3(blocks), dim3(256), 0, p.stream, p.ws, p.grid, E, eb, p.N,
+                           static_cast<double*>(p.Y), p.ldy);
+    else
+        hipLaunchKernelGGL((tsg::fold_partials<1>), dim3(blocks), dim3(256), 0, p.stream, p.ws, p.grid, E, eb, p.N,
+                           static_cast<double*>(p.Y), p.ldy);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -227,10 +279,11 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
     DeviceInfo di;
     if ((s = device_info(dev, &di)) != TSG_OK) return s;
     const tsg::Variant* v = pick(tsg::OP_TSMTTSM, dt, M, N, A, lda, B, ldb);
-    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMTTSM %dx%d", M, N);
+    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMTTSM %dx%d%s", M, N,
+                        g_force.empty() ? "" : " (a forced variant does not apply)");
     tsg::Launch p{};
     p.stream = static_cast<hipStream_t>(stream);
-    p.grid = grid_for(dev, *v, K, di.cus);
+    p.grid = grid_for(dev, *v, K, M, N, di.cus);
     p.K = K;
     p.M = M;
     p.N = N;
@@ -244,13 +297,12 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
     Workspace* w = nullptr;
     if ((s = get_workspace(dev, p.stream, tsmttsm_ws_bytes(p.grid, M, N, is_complex(dt)), &w)) != TSG_OK)
         return s;
-    if ((size_t)(p.grid + kGroup - 1) / kGroup + 1 > (size_t)kCounterSlots)
-        return fail(TSG_E_UNSUPPORTED, "grid of %d blocks exceeds the counter slots", p.grid);
     p.ws = static_cast<double*>(w->data);
-    p.cnt = w->counters;
     v->launch(p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
+    if (p.grid > 1 && (e = launch_fold(p, is_complex(dt))) != hipSuccess)
+        return fail(TSG_E_HIP, "launch of the partial fold: %s", hipGetErrorString(e));
     return TSG_OK;
 }
 
@@ -266,10 +318,11 @@ tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N
     DeviceInfo di;
     if ((s = device_info(dev, &di)) != TSG_OK) return s;
     const tsg::Variant* v = pick(tsg::OP_TSMM, dt, M, N, A, lda, B, ldb);
-    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMM %dx%d", M, N);
+    if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMM %dx%d%s", M, N,
+                        g_force.empty() ? "" : " (a forced variant does not apply)");
     tsg::Launch p{};
     p.stream = static_cast<hipStream_t>(stream);
-    p.grid = grid_for(dev, *v, K, di.cus);
+    p.grid = grid_for(dev, *v, K, M, N, di.cus);
     p.K = K;
     p.M = M;
     p.N = N;
@@ -297,7 +350,7 @@ size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N)
     if (device_info(dev, &di) != TSG_OK) return 0;
     const tsg::Variant* v = pick(tsg::OP_TSMTTSM, dt, M, N, nullptr, M + (M & 1), nullptr, N + (N & 1));
     if (!v) return 0;
-    return tsmttsm_ws_bytes(grid_for(dev, *v, K, di.cus), M, N, is_complex(dt));
+    return tsmttsm_ws_bytes(grid_for(dev, *v, K, M, N, di.cus), M, N, is_complex(dt));
 }
 
 tsg_status tsg_reserve(tsg_dtype dt, int64_t K, int32_t M, int32_t N, void* stream)
@@ -316,7 +369,7 @@ tsg_status tsg_reserve(tsg_dtype dt, int64_t K, int32_t M, int32_t N, void* stre
         const tsg::Variant& v = tsg::kVariants[i];
         if (v.op != tsg::OP_TSMTTSM || v.dt != (int)dt) continue;
         if (!((v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN))) continue;
-        size_t b = tsmttsm_ws_bytes(grid_for(dev, v, K, di.cus), M, N, is_complex(dt));
+        size_t b = tsmttsm_ws_bytes(grid_for(dev, v, K, M, N, di.cus), M, N, is_complex(dt));
         if (b > need) need = b;
     }
     Workspace* w;
@@ -342,7 +395,6 @@ void tsg_finalize(void)
     for (auto& kv : g_ws) {
         hipSetDevice(kv.first.first);
         if (kv.second.data) hipFree(kv.second.data);
-        if (kv.second.counters) hipFree(kv.second.counters);
     }
     g_ws.clear();
     g_occ.clear();
@@ -363,6 +415,25 @@ const char* tsg_status_string(tsg_status s)
 }
 
 const char* tsg_last_error(void) { return g_err.c_str(); }
+
+tsg_status tsg_force_variant(const char* name)
+{
+    g_err.clear();
+    if (!name || !*name) {
+        g_force.clear();
+        return TSG_OK;
+    }
+    for (int i = 0; i < tsg::kNumVariants; ++i)
+        if (!strcmp(tsg::kVariants[i].name, name)) {
+            g_force = name;
+            return TSG_OK;
+        }
+    return fail(TSG_E_ARG, "no kernel variant named %s", name);
+}
+
+int32_t tsg_variant_count(void) { return tsg::kNumVariants; }
+
+const char* tsg_variant_name(int32_t i) { return (i >= 0 && i < tsg::kNumVariants) ? tsg::kVariants[i].name : ""; }
 
 const char* tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t M, int32_t N)
 {

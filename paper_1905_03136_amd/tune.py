@@ -1,0 +1,222 @@
+"""Autotuner: exhaustive timing of the generated configurations.
+
+The paper picks the best configuration of every matrix size by an exhaustive
+search over the generator's options (Section 5.1; Sections 6.1-6.3 show the
+cross sections of that search).  Here the candidate space of a width comes
+from ``codegen.candidates`` (mapping, rows in flight, waves per block, wave
+split of C), already pruned by a register model.
+
+    python -m paper_1905_03136_amd.tune build            # CPU: compile every candidate
+    python -m paper_1905_03136_amd.tune run --db DB.jsonl --out tuned.json   # GPU
+
+``run`` times each candidate at K rows (default 2^24), rotating through
+enough disjoint buffer sets that consecutive calls never find their data in
+the 256 MB Infinity Cache, and checks that every candidate reproduces the
+first candidate's result bit for bit on integer-valued inputs (exact in
+binary64, so all correct mappings agree).  Records are appended to a JSONL
+database, so an interrupted run resumes where it stopped; ``tuned.json``
+keeps the fastest correct configuration per (operation, dtype, M, N) and is
+read by the code generator when the product library is built.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+TUNE_LIB = os.path.join(HERE, "libtsgemm_tune.so")
+HBM_PEAK = 8.0e12
+FP64_PEAK = 78.6e12
+
+
+def _widths(name):
+    from paper_1905_03136_amd import codegen
+    if name == "graded":
+        return codegen.GRADED
+    if name == "square":
+        return codegen.SQUARE_ALL
+    out = []
+    for tok in name.split(","):
+        m, n = tok.split("x")
+        out.append((int(m), int(n)))
+    return out
+
+
+def cmd_build(args):
+    sys.path.insert(0, ROOT)
+    from paper_1905_03136_amd import build, codegen
+    variants = codegen.tuning_variants(_widths(args.widths))
+    build.build(variants=variants, lib_path=TUNE_LIB, tag="_tune")
+
+
+def _algorithmic(op, cplx, K, M, N):
+    s = 16 if cplx else 8
+    return s * (K * M + K * N + M * N), (8 if cplx else 2) * M * N * K
+
+
+def cmd_run(args):
+    os.environ.setdefault("TSG_LIBRARY", TUNE_LIB)
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_1905_03136_amd import _lib, api, codegen, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K = args.K
+    widths = _widths(args.widths)
+    groups = {}
+    for v in codegen.tuning_variants(widths):
+        if v["M"] == 0:
+            continue
+        groups.setdefault((v["op"], v["dt"], v["M"], v["N"]), []).append(v)
+    done = {}
+    if os.path.exists(args.db):
+        with open(args.db) as f:
+            for line in f:
+                try:
+                    r = json.loads(line)
+                    done[r["name"]] = r
+                except ValueError:
+                    pass
+    names = {_lib.tsg_variant_name(i) for i in range(_lib.tsg_variant_count())}
+    pool_elems = 2 * K * 64
+    pools = {}
+    for cplx in (False, True):
+        t = torch.empty(pool_elems * (2 if cplx else 1), dtype=torch.float64, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(1234 + int(cplx))
+        t.uniform_(-1.0, 1.0, generator=g)
+        pools[cplx] = t
+    db = open(args.db, "a")
+    t_start = time.time()
+    for key in sorted(groups, key=lambda k: (k[0], k[1], k[2] * k[3])):
+        op, dt, M, N = key
+        cplx = dt == "c128"
+        cw = 2 if cplx else 1
+        tdt = torch.complex128 if cplx else torch.float64
+        cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
+        if not cands:
+            continue
+        # integer-valued reference problem (exact in binary64): all candidates must agree bit for bit
+        kc = 4099
+        Ai = torch.from_numpy(inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)).to(dev)
+        Bi = torch.from_numpy(inputs.host_integers(kc, N, 7, inputs.STREAM_B, cplx)).to(dev)
+        Xi = torch.from_numpy(inputs.host_integers(M, N, 7, inputs.STREAM_C, cplx)).to(dev)
+        # buffer sets for timing
+        ws_elems = K * (M + N) * cw
+        ws_bytes = ws_elems * 8
+        R = max(1, min(int(math.ceil((1 << 30) / ws_bytes)), pool_elems * cw // ws_elems))
+        sets = []
+        for r in range(R):
+            base = pools[cplx][r * ws_elems:(r + 1) * ws_elems]
+            a = base[:K * M * cw]
+            b = base[K * M * cw:]
+            if cplx:
+                a = torch.view_as_complex(a.view(K, M, 2))
+                b = torch.view_as_complex(b.view(K, N, 2))
+            else:
+                a = a.view(K, M)
+                b = b.view(K, N)
+            sets.append((a, b))
+        Xs = inputs.device_uniform(M, N, 3, inputs.STREAM_C, cplx, dev)
+        Cout = torch.empty((M, N), dtype=tdt, device=dev)
+        byts, flops = _algorithmic(op, cplx, K, M, N)
+        ref = None
+        for v in cands:
+            name = codegen.variant_name(v)
+            rec = dict(op=op, dt=dt, M=M, N=N, name=name, cfg=v["cfg"], K=K)
+            if name not in names:
+                rec.update(ok=False, error="not compiled")
+                db.write(json.dumps(rec) + "\n")
+                continue
+            _lib.check(_lib.tsg_force_variant(name))
+            try:
+                if op == "tsmttsm":
+                    res = api.tsmttsm(Ai, Bi).clone()
+                    call = (lambda s: api.tsmttsm(s[0], s[1], out=Cout))
+                else:
+                    res = api.tsmm(Ai, Xi).clone()
+                    call = (lambda s: api.tsmm(s[0], Xs, out=s[1]))
+                if ref is None:
+                    ref = res
+                ok = bool(torch.equal(res, ref))
+                for w in range(args.warmup):
+                    call(sets[w % R])
+                evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(args.reps)]
+                for i in range(args.reps):
+                    evs[i][0].record()
+                    call(sets[(args.warmup + i) % R])
+                    evs[i][1].record()
+                torch.cuda.synchronize()
+                times = sorted(e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs)
+                t = times[len(times) // 2]
+                roof = max(byts / HBM_PEAK, flops / FP64_PEAK)
+                rec.update(ok=ok, us=round(t * 1e6, 2), us_min=round(times[0] * 1e6, 2),
+                           GBps=round(byts / t / 1e9, 1), GFLOPs=round(flops / t / 1e9, 1),
+                           roof_frac=round(roof / t, 4))
+            finally:
+                _lib.tsg_force_variant(None)
+            db.write(json.dumps(rec) + "\n")
+            db.flush()
+            done[name] = rec
+            print("[tune] %-50s %9.1f us %7.1f GB/s roof %.3f %s" % (
+                name, rec.get("us", -1), rec.get("GBps", 0), rec.get("roof_frac", 0), "" if rec["ok"] else "MISMATCH"),
+                flush=True)
+    db.close()
+    print("[tune] done in %.0f s" % (time.time() - t_start), flush=True)
+    write_table(args.db, args.out)
+
+
+def write_table(db_path, out_path):
+    """Fastest correct configuration per (op, dtype, M, N) from the database."""
+    best = {}
+    with open(db_path) as f:
+        for line in f:
+            try:
+                r = json.loads(line)
+            except ValueError:
+                continue
+            if not r.get("ok") or "us" not in r:
+                continue
+            key = (r["op"], r["dt"], r["M"], r["N"])
+            if key not in best or r["us"] < best[key]["us"]:
+                best[key] = r
+    entries = [dict(op=k[0], dt=k[1], M=k[2], N=k[3], cfg=r["cfg"], name=r["name"], us=r["us"],
+                    GBps=r["GBps"], roof_frac=r["roof_frac"], K=r["K"])
+               for k, r in sorted(best.items(), key=lambda kv: (kv[0][0], kv[0][1], kv[0][2] * kv[0][3]))]
+    with open(out_path, "w") as f:
+        json.dump({"entries": entries}, f, indent=1)
+        f.write("\n")
+    print("[tune] wrote %s (%d entries)" % (out_path, len(entries)), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("build")
+    b.add_argument("--widths", default="graded")
+    r = sub.add_parser("run")
+    r.add_argument("--widths", default="graded")
+    r.add_argument("--K", type=int, default=1 << 24)
+    r.add_argument("--db", default="gpurun_out/tune_db.jsonl")
+    r.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
+    r.add_argument("--reps", type=int, default=5)
+    r.add_argument("--warmup", type=int, default=2)
+    t = sub.add_parser("table")
+    t.add_argument("--db", default="gpurun_out/tune_db.jsonl")
+    t.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
+    a = ap.parse_args(argv)
+    if a.cmd == "build":
+        cmd_build(a)
+    elif a.cmd == "run":
+        cmd_run(a)
+    else:
+        write_table(a.db, a.out)
+
+
+if __name__ == "__main__":
+    main()

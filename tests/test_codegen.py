@@ -42,4 +42,4 @@ def test_default_configs_respect_register_budget():
                 if c["kind"] == "valu" and op == "tsmttsm":
                     assert w * w * cw + 2 * c["U"] * 2 * w * cw <= 100
                 if c["kind"] == "mfma" and op == "tsmttsm":
-                    assert c["MB"] * c["NB"] * 4 * cw <= 64 or c["MW"] > 1
+                    assert c["MB"] * c["NB"] * 4 * cw <= 64
