@@ -54,11 +54,14 @@ def candidates(op, dt, M, N):
     cw = 2 if DTYPES[dt][1] else 1
     cplx = DTYPES[dt][1]
     out = []
+    # Register sets in flight (leap-frog ring depth): 2 = current + next.
+    # 512-thread blocks cap a lane at 256 registers in all (VGPR + AGPR).
     if op == "tsmttsm":
         if M <= 16 and N <= 16:
             for u in (1, 2, 4, 8):
                 for w in (4, 8):
-                    out.append(dict(kind="packed", U=u, WPB=w))
+                    for nbuf in (2, 4):
+                        out.append(dict(kind="packed", U=u, WPB=w, NBUF=nbuf))
         if M * N * cw <= 64:
             for u in (1, 2, 4):
                 if _valu_regs(op, M, N, cw, u) <= 110:
@@ -67,21 +70,27 @@ def candidates(op, dt, M, N):
         if M > 8 or N > 8:
             mbt, nb = _ceil(M, 16), _ceil(N, 16)
             for mw in (1, 2, 4):
-                if mbt % mw and mw > 1:
-                    continue
-                if mw > mbt:
+                if (mbt % mw and mw > 1) or mw > mbt:
                     continue
                 mb = _ceil(mbt, mw)
-                for u in (1, 2, 4):
-                    for w in (4, 8):
-                        if w % mw:
-                            continue
-                        c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w)
-                        acc = mb * nb * 4 * cw
-                        # 512-thread blocks cap a lane at 256 registers in all
-                        acc_cap = 48 if w == 8 else 64
-                        if acc <= acc_cap and 2 * u * (mb + nb) * cw <= 48:
+                acc = mb * nb * 4 * cw
+                for w in (4, 8):
+                    if w % mw or acc > 64:
+                        continue
+                    for u in (1, 2, 4):
+                        for nbuf in (2, 3, 4):
+                            ops = nbuf * u * (mb + nb) * cw
+                            if ops > 72 or (nbuf > 2 and u > 2):
+                                continue
+                            # two waves per SIMD (OCC = 2, implied by 512-thread
+                            # blocks) leave each lane 256 registers in all
+                            two = acc + ops <= 104
+                            if w == 8 and not two:
+                                continue
+                            c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf)
                             out.append(c)
+                            if w == 4 and two and mw > 1:
+                                out.append(dict(c, OCC=2))
         return out
     if M * cw <= 8 and N * cw <= 8:
         for u in (1, 2, 4):
@@ -90,14 +99,18 @@ def candidates(op, dt, M, N):
     if N <= 16 and M <= 16 and _ceil((16 // N) * M, 4) <= 16:
         for u in (1, 2, 4):
             for w in (4, 8):
-                out.append(dict(kind="packed", U=u, WPB=w))
+                for nbuf in (2, 4):
+                    out.append(dict(kind="packed", U=u, WPB=w, NBUF=nbuf))
     if M >= 4 or N >= 16:
         ms, nb = _ceil(M, 4), _ceil(N, 16)
         for u in (1, 2, 4):
             for w in (4, 8):
-                c = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)
-                if _mfma_regs(op, M, N, cw, c) <= 160:
-                    out.append(c)
+                for nbuf in (2, 3, 4):
+                    ops = nbuf * u * ms * cw + u * nb * 4 * cw
+                    if ops <= (96 if w == 8 else 160) and (nbuf == 2 or u <= 2):
+                        if not cplx and M % 8 == 0:
+                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, VA=1))
+                        out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
     return out
 
 
@@ -204,6 +217,12 @@ def variant_name(v):
         tag = "mfma_s%dn%d_u%d" % (c["MS"], c["NB"], c["U"])
     if c.get("WPB", WPB) != WPB:
         tag += "_w%d" % c["WPB"]
+    if c.get("NBUF", 2) != 2:
+        tag += "_r%d" % c["NBUF"]
+    if c["kind"] == "mfma" and c.get("VA"):
+        tag += "_v2"
+    if c.get("OCC", 1) != 1:
+        tag += "_o%d" % c["OCC"]
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -211,20 +230,22 @@ def _template(v):
     c = v["cfg"]
     cplx = "true" if DTYPES[v["dt"]][1] else "false"
     M, N = v["M"], v["N"]
+    nbuf = c.get("NBUF", 2)
     if c["kind"] == "packed":
-        return "tsg::%s_packed<%d, %d, %d, %s, %d>" % (v["op"], M, N, c["U"], cplx, c["WPB"])
+        return "tsg::%s_packed<%d, %d, %d, %s, %d, %d>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf)
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
                 M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
                 "true" if c["VB"] else "false", c["WPB"])
-        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d>" % (
-            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"])
+        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1))
     if c["kind"] == "valu":
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d>" % (M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"])
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d>" % (
+        M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false", c.get("OCC", 1))
 
 
 def rows_per_tile(v):
@@ -253,7 +274,7 @@ def _launcher(v, fn):
 
 def _record(v, fn):
     c = v["cfg"]
-    pair_a = int(c["kind"] == "valu" and bool(c.get("VA")))
+    pair_a = int(c["kind"] in ("valu", "mfma") and bool(c.get("VA")))
     pair_x = int(c["kind"] == "valu" and bool(c.get("VB")))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)

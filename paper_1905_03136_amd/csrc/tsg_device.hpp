@@ -68,6 +68,55 @@ __device__ __forceinline__ void leapfrog(int64_t t, int64_t ntiles, int64_t G, B
     }
 }
 
+// Deeper leap frogging: NBUF register sets in a ring, loads issued NBUF - 1
+// tiles ahead of the multiplication.  Every pass of the (fully unrolled) ring
+// issues the same loads, so the compiler waits only for the oldest set; near
+// the end of a block's tiles the look-ahead index is clamped to the block's
+// last tile (a repeated, cache-resident load instead of a conditional one).
+template <int NBUF, class Buf, class Load, class Compute>
+__device__ __forceinline__ void leapfrog_ring(int64_t t0, int64_t ntiles, int64_t G, Buf (&buf)[NBUF], Load load,
+                                              Compute compute)
+{
+    static_assert(NBUF >= 2, "a ring needs two register sets at least");
+    if (t0 >= ntiles) return;
+    const int64_t last = ntiles - 1 - ((ntiles - 1 - t0) % G);
+#pragma unroll
+    for (int i = 0; i < NBUF - 1; ++i) {
+        const int64_t ti = t0 + i * G;
+        load(ti <= last ? ti : last, buf[i]);
+    }
+    int64_t t = t0;
+    while (true) {
+#pragma unroll
+        for (int p = 0; p < NBUF; ++p) {
+            const int64_t ta = t + (NBUF - 1) * G;
+            load(ta <= last ? ta : last, buf[(p + NBUF - 1) % NBUF]);
+            compute(t, buf[p]);
+            t += G;
+            if (t > last) return;
+        }
+    }
+}
+
+// Dispatch: two sets use the unclamped ping-pong loop, more use the ring.
+template <int NBUF, class Buf, class Load, class Compute>
+__device__ __forceinline__ void pipeline(int64_t t0, int64_t ntiles, int64_t G, Buf (&buf)[NBUF], Load load,
+                                         Compute compute)
+{
+    if constexpr (NBUF == 2)
+        leapfrog(t0, ntiles, G, buf[0], buf[1], load, compute);
+    else
+        leapfrog_ring<NBUF>(t0, ntiles, G, buf, load, compute);
+}
+
+// Cached load, for operands that several waves of a block read.
+__device__ __forceinline__ double ld_shared(const double* p) { return *p; }
+__device__ __forceinline__ zd ld_shared(const zd* p)
+{
+    const dbl2 v = *reinterpret_cast<const dbl2*>(p);
+    return zd{v.x, v.y};
+}
+
 // -------------------------------------------------- wave reduction (fixed tree)
 __device__ __forceinline__ double wave_sum(double v)
 {

@@ -55,8 +55,8 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
 // Output layout of the 16x16 FP64 accumulator (checked on gfx950 with an
 // in-bounds probe): lane l, element r holds D(l / 16 + 4 r, l % 16).
 // ============================================================================
-template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB>
-__global__ void __launch_bounds__(WPB * kWave)
+template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1>
+__global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
              double* __restrict__ ws, int conj)
@@ -109,7 +109,7 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
         T a[U][MB];
         T b[U][NB];
     };
-    Frag x, y;
+    Frag fr[NBUF];
     auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -121,7 +121,13 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
             for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok && mok[i], ld_stream(ar + moff[i]));
 #pragma unroll
-            for (int j = 0; j < NB; ++j) f.b[u][j] = keep(ok && nok[j], ld_stream(br + noff[j]));
+            for (int j = 0; j < NB; ++j) {
+                // with MW > 1 the waves of a row group read the same B: keep it in cache
+                if constexpr (MW > 1)
+                    f.b[u][j] = keep(ok && nok[j], ld_shared(br + noff[j]));
+                else
+                    f.b[u][j] = keep(ok && nok[j], ld_stream(br + noff[j]));
+            }
         }
     };
     auto compute = [&](int64_t, Frag& f) {
@@ -133,18 +139,25 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
                     for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i], f.b[u][j], acc[i][j]);
             } else {
+                // All products with Re(a) first, then those with Im(a): the two
+                // updates of one accumulator are 2 MB NB instructions apart
+                // instead of back to back.
                 double nbi[NB];
 #pragma unroll
                 for (int j = 0; j < NB; ++j) nbi[j] = -f.b[u][j].im;
 #pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        acc[i][j] = mfma16(f.a[u][i].re, f.b[u][j].re, acc[i][j]);
+                        acci[i][j] = mfma16(f.a[u][i].re, f.b[u][j].im, acci[i][j]);
+                    }
+#pragma unroll
                 for (int i = 0; i < MB; ++i) {
-                    const double ar = f.a[u][i].re;
                     const double ai = conj ? -f.a[u][i].im : f.a[u][i].im;
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
-                        acc[i][j] = mfma16(ar, f.b[u][j].re, acc[i][j]);
                         acc[i][j] = mfma16(ai, nbi[j], acc[i][j]);
-                        acci[i][j] = mfma16(ar, f.b[u][j].im, acci[i][j]);
                         acci[i][j] = mfma16(ai, f.b[u][j].re, acci[i][j]);
                     }
                 }
@@ -152,7 +165,7 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
         }
     };
     const int64_t ntiles = (K + RT - 1) / RT;
-    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
 
     // Fold the row groups into the block partial, one group after the other.
     const int E = M * N * CW;
@@ -193,7 +206,7 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // throughput for the low arithmetic intensity of these widths (Eq. 1: M/8
 // flop per byte), so the unused products cost no time.
 // ============================================================================
-template <int MC, int NC, int U, bool CPLX, int WPB>
+template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
@@ -229,7 +242,7 @@ tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t l
         T a[U];
         T b[U];
     };
-    Frag x, y;
+    Frag fr[NBUF];
     auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -248,14 +261,14 @@ tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t l
             } else {
                 const double ai = conj ? -f.a[u].im : f.a[u].im;
                 acc = mfma16(f.a[u].re, f.b[u].re, acc);
-                acc = mfma16(ai, -f.b[u].im, acc);
                 acci = mfma16(f.a[u].re, f.b[u].im, acci);
+                acc = mfma16(ai, -f.b[u].im, acc);
                 acci = mfma16(ai, f.b[u].re, acci);
             }
         }
     };
     const int64_t ntiles = (K + RT - 1) / RT;
-    leapfrog(blockIdx.x, ntiles, (int64_t)gridDim.x, x, y, load, compute);
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
 
     // D(i, j) with i = lane / 16 + 4 r, j = lane % 16 -> LDS, then the diagonal
     // blocks (i / M == j / N) are summed over packed rows and waves in order.
@@ -562,12 +575,17 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // rows l/16 + 4r (r < 4) of column l%16 of each 16 x 16 output block: sixteen
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
-template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB>
-__global__ void __launch_bounds__(WPB * kWave)
+template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1>
+__global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
           double alpha, double beta, int conj)
 {
+    // VA: A is read with 16-byte loads, A(row, 8t + 2q .. 8t + 2q + 1) for the
+    // lane of k-slot q, which serve the steps s = 2t (even column) and 2t + 1
+    // (odd column); the contraction order over m is permuted accordingly,
+    // m(s, q) = 8 (s / 2) + 2 q + s % 2, and C is staged in the same order.
+    static_assert(!VA || (!CPLX && MS % 2 == 0), "paired A loads: real data, M a multiple of 8");
     using T = elem_t<CPLX>;
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RT = 16 * U * WPB;
@@ -584,12 +602,13 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     const int lc = lane & 15;
     const bool read_b = beta != 0.0;
 
-    // Stage C in fragment order: cf[(s * NB + j) * 64 + l] = C(4s + l/16, 16j + l%16).
+    // Stage C in fragment order: cf[(s * NB + j) * 64 + l] = C(m(s, l/16), 16j + l%16).
     for (int idx = threadIdx.x; idx < NFRAG; idx += blockDim.x) {
         const int l = idx & (kWave - 1);
         const int sj = idx / kWave;
         const int s = sj / NB, j = sj - (sj / NB) * NB;
-        const int m = 4 * s + (l >> 4), n = 16 * j + (l & 15);
+        const int m = VA ? 8 * (s >> 1) + 2 * (l >> 4) + (s & 1) : 4 * s + (l >> 4);
+        const int n = 16 * j + (l & 15);
         const bool ok = m < M && n < N;
         if constexpr (CPLX) {
             cf[idx] = ok ? Cm[2 * ((int64_t)m * ldc + n)] : 0.0;
@@ -604,7 +623,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     bool kok[MS];
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
-        const int m = 4 * s + lr;
+        const int m = VA ? 8 * (s >> 1) + 2 * lr : 4 * s + lr;  // VA: first column of the pair
         kok[s] = m < M;
         koff[s] = kok[s] ? m : 0;
     }
@@ -612,15 +631,24 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     struct Frag {
         T a[U][MS];
     };
-    Frag x, y;
+    Frag fr[NBUF];
     auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lc;
             const int64_t rc = row < K ? row : K - 1;
             const T* ar = A + rc * lda;
+            if constexpr (VA) {
 #pragma unroll
-            for (int s = 0; s < MS; ++s) f.a[u][s] = keep(kok[s], ld_stream(ar + koff[s]));
+                for (int s = 0; s < MS; s += 2) {
+                    const dbl2 v = ld_stream2(reinterpret_cast<const double*>(ar) + koff[s]);
+                    f.a[u][s] = keep(kok[s], v.x);
+                    f.a[u][s + 1] = keep(kok[s], v.y);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < MS; ++s) f.a[u][s] = keep(kok[s], ld_stream(ar + koff[s]));
+            }
         }
     };
     auto compute = [&](int64_t t, Frag& f) {
@@ -637,27 +665,40 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 if constexpr (CPLX) acci[u][j] = dbl4{0.0, 0.0, 0.0, 0.0};
             }
 #pragma unroll
-        for (int s = 0; s < MS; ++s)
+        for (int s = 0; s < MS; ++s) {
+            if constexpr (!CPLX) {
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const double cr = cf[(s * NB + j) * kWave + lane];
-                if constexpr (!CPLX) {
+                for (int j = 0; j < NB; ++j) {
+                    const double cr = cf[(s * NB + j) * kWave + lane];
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s], cr, acc[u][j]);
-                } else {
-                    const double ci = cf[NFRAG + (s * NB + j) * kWave + lane];
-                    const double nci = -ci;
+                }
+            } else {
+                // products with Re(a) for every block first, then those with
+                // Im(a), so that dependent updates of one accumulator are apart
+                double cr[NB], ci[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    cr[j] = cf[(s * NB + j) * kWave + lane];
+                    ci[j] = cf[NFRAG + (s * NB + j) * kWave + lane];
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const double ar = f.a[u][s].re;
-                        const double ai = conj ? -f.a[u][s].im : f.a[u][s].im;
-                        acc[u][j] = mfma16(ar, cr, acc[u][j]);
-                        acc[u][j] = mfma16(ai, nci, acc[u][j]);
-                        acci[u][j] = mfma16(ar, ci, acci[u][j]);
-                        acci[u][j] = mfma16(ai, cr, acci[u][j]);
+                        acc[u][j] = mfma16(f.a[u][s].re, cr[j], acc[u][j]);
+                        acci[u][j] = mfma16(f.a[u][s].re, ci[j], acci[u][j]);
                     }
-                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const double ai = conj ? -f.a[u][s].im : f.a[u][s].im;
+                        acc[u][j] = mfma16(ai, -ci[j], acc[u][j]);
+                        acci[u][j] = mfma16(ai, cr[j], acci[u][j]);
+                    }
             }
+        }
         const bool full = (t + 1) * RT <= K;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -690,7 +731,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         }
     };
     const int64_t ntiles = (K + RT - 1) / RT;
-    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
 }
 
 // ============================================================================
@@ -705,7 +746,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // otherwise (a block-diagonal copy of C, staged once per block in LDS in
 // fragment order).  A lane's A operand for pair q is A(k0 + i P + h, m).
 // ============================================================================
-template <int MC, int NC, int U, bool CPLX, int WPB>
+template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
@@ -770,7 +811,7 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     struct Frag {
         T a[U][S];
     };
-    Frag x, y;
+    Frag fr[NBUF];
     auto load = [&](int64_t t, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -838,7 +879,7 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         }
     };
     const int64_t ntiles = (K + RT - 1) / RT;
-    leapfrog(blockIdx.x, ntiles, (int64_t)gridDim.x, x, y, load, compute);
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
 }
 
 }  // namespace tsg

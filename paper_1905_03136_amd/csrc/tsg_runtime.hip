@@ -20,9 +20,10 @@ namespace tsg {
 
 // Sum of the G per-block partials of a TSMTTSM launch (slot b holds E doubles
 // at ws + b * E) into C, in a fixed order: each block takes EB consecutive
-// entries (EB a power of two <= 64) and 256 / EB slices; slice s sums slots
-// s, s + S, s + 2S, ... in increasing order, and the slices are combined by a
-// fixed pairwise tree.  The result is bitwise reproducible for a given grid.
+// entries (EB a power of two <= 8) and S = 256 / EB slices; slice s sums slots
+// s, s + S, s + 2S, ... in increasing order (loads issued eight at a time, the
+// additions in slot order), and the slices are combined by a fixed pairwise
+// tree.  The result is bitwise reproducible for a given grid.
 template <int CW>
 __global__ void __launch_bounds__(256)
 fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double* __restrict__ C, int64_t ldc)
@@ -33,8 +34,17 @@ fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double
     const int s = threadIdx.x / EB;
     const int e = blockIdx.x * EB + el;
     double v = 0.0;
-    if (e < E)
-        for (int b = s; b < G; b += S) v += ws[(size_t)b * E + e];
+    if (e < E) {
+        int b = s;
+        for (; b + 7 * S < G; b += 8 * S) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ws[(size_t)(b + u * S) * E + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v += x[u];
+        }
+        for (; b < G; b += S) v += ws[(size_t)b * E + e];
+    }
     red[threadIdx.x] = v;
     __syncthreads();
     for (int h = S / 2; h >= 1; h >>= 1) {
@@ -252,7 +262,7 @@ hipError_t launch_fold(const tsg::Launch& p, bool cplx)
 {
     const int E = p.M * p.N * (cplx ? 2 : 1);
     int eb = 1;
-    while (eb < E && eb < 64) eb <<= 1;
+    while (eb < E && eb < 8) eb <<= 1;
     const int blocks = (E + eb - 1) / eb;
     if (cplx)
         hipLaunchKernelGGL((tsg::fold_partials<2>), dim3(blocks), dim3(256), 0, p.stream, p.ws, p.grid, E, eb, p.N,

@@ -2,7 +2,7 @@
 // bandwidth b_s of the roofline (the paper measures b_s the same way: a
 // read-only thread-local sum for TSMTTSM and a read + write stream for TSMM,
 // Section 1.6 and Table 1).  Both stream 16-byte non-temporal accesses with a
-// grid-stride loop and UNR loads in flight per lane.
+// grid-stride loop over contiguous chunks and kUnroll loads in flight per lane.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,19 +14,24 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int kThreads = 256;
 constexpr int kUnroll = 8;
 
+// Each block streams contiguous chunks of kThreads * kUnroll 16-byte elements
+// (32 KB), chunk c = blockIdx.x + i * gridDim.x; a wave's load instruction
+// covers 1 KB of consecutive bytes.  The tail beyond whole chunks is handled
+// element by element.
 __global__ void __launch_bounds__(kThreads) stream_read(const d2* __restrict__ x, int64_t n, double* __restrict__ sink)
 {
+    constexpr int64_t CH = (int64_t)kThreads * kUnroll;
     double s = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
+    const int64_t nch = n / CH;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const d2* p = x + c * CH + threadIdx.x;
         d2 v[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(x + i + u * stride);
+        for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(p + u * kThreads);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) s += v[u].x + v[u].y;
     }
-    for (; i < n; i += stride) {
+    for (int64_t i = nch * CH + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const d2 v = __builtin_nontemporal_load(x + i);
         s += v.x + v.y;
     }
@@ -36,16 +41,18 @@ __global__ void __launch_bounds__(kThreads) stream_read(const d2* __restrict__ x
 
 __global__ void __launch_bounds__(kThreads) stream_copy(const d2* __restrict__ x, d2* __restrict__ y, int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    for (; i + (kUnroll - 1) * stride < n; i += kUnroll * stride) {
+    constexpr int64_t CH = (int64_t)kThreads * kUnroll;
+    const int64_t nch = n / CH;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t o = c * CH + threadIdx.x;
         d2 v[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(x + i + u * stride);
+        for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(x + o + u * kThreads);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) __builtin_nontemporal_store(v[u], y + i + u * stride);
+        for (int u = 0; u < kUnroll; ++u) __builtin_nontemporal_store(v[u], y + o + u * kThreads);
     }
-    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
+    for (int64_t i = nch * CH + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
 int grid_of(int blocks_per_cu)
