@@ -70,6 +70,63 @@ def measure_bs(torch, src, dst, nbytes=8 << 30, reps=5):
     return out
 
 
+def time_call(torch, fn, reps=3, warmup=1):
+    """Median device time of fn() over `reps` runs (events on the current stream)."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return sorted(ts)[len(ts) // 2]
+
+
+def precision_form(torch, api, inputs, dev, K=1 << 25, widths=(8, 32, 64)):
+    """Speedup of binary32 storage (exact products, binary64 accumulation)
+    over binary64 storage for both products, real and complex, at K = 2^25."""
+    out = []
+    for cplx in (False, True):
+        t64 = torch.complex128 if cplx else torch.float64
+        t32 = torch.complex64 if cplx else torch.float32
+        A = inputs.device_uniform(K, 64, 7, inputs.STREAM_A, cplx, dev)
+        B = inputs.device_uniform(K, 64, 7, inputs.STREAM_B, cplx, dev)
+        A32, B32 = A.to(t32), B.to(t32)
+        X = inputs.device_uniform(64, 64, 7, inputs.STREAM_C, cplx, dev)
+        for w in widths:
+            a64 = A.reshape(-1)[:K * w].view(K, w)
+            b64 = B.reshape(-1)[:K * w].view(K, w)
+            a32 = A32.reshape(-1)[:K * w].view(K, w)
+            b32 = B32.reshape(-1)[:K * w].view(K, w)
+            x = X[:w, :w].contiguous()
+            rec = {"dtype": "Z" if cplx else "D", "M": w, "N": w, "K": K}
+            for op in ("tsmttsm", "tsmm"):
+                if op == "tsmttsm":
+                    f64 = (lambda: api.tsmttsm(a64, b64))
+                    f32 = (lambda: api.tsmttsm(a32, b32))
+                else:
+                    f64 = (lambda: api.tsmm(a64, x, out=b64))
+                    f32 = (lambda: api.tsmm(a32, x, out=b32))
+                t_64 = time_call(torch, f64)
+                t_32 = time_call(torch, f32)
+                s = 16 if cplx else 8
+                rec[op] = {"us_fp64": round(t_64 * 1e6, 1), "us_fp32": round(t_32 * 1e6, 1),
+                           "speedup": round(t_64 / t_32, 3),
+                           "GBps_fp32": round((s // 2) * K * 2 * w / t_32 / 1e9, 1),
+                           "kernel_fp32": api.kernel_name(op, t32, w, w)}
+            out.append(rec)
+        del A, B, A32, B32
+        torch.cuda.empty_cache()
+    return {"note": "binary32 / complex64 storage of A and B (values widened exactly, products exact, "
+                    "binary64 accumulation and reduction) against binary64 / complex128 storage; arithmetic "
+                    "error against the binary64 oracle on the stored values is at the binary64 level "
+                    "(tests check <= 1e-12 for TSMTTSM, one binary32 rounding for TSMM outputs)",
+            "widths": out}
+
+
 def cpu_baseline(K_sample):
     import numpy as np
 
@@ -108,6 +165,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=1 << 15, help="rows of the oracle sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "
@@ -217,6 +275,11 @@ def main():
                         "(read for TSMTTSM, copy for TSMM) instead of the 8 TB/s spec"},
         "widths": per,
     }
+    if not a.no_forms:
+        del bufA, bufB, calls
+        torch.cuda.empty_cache()
+        print("[bench] precision form (binary32 storage) at K=2^25", file=sys.stderr, flush=True)
+        out["precision_form"] = precision_form(torch, api, inputs, dev)
     if a.cpu_sample > 0:
         print("[bench] timing the CPU oracle on a %d-row sample" % a.cpu_sample, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)

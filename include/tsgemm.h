@@ -60,10 +60,13 @@ typedef enum {
 
 /* op(A) of TSMTTSM: the transpose, or for complex types the conjugate
  * transpose (the Hermitian product A^H B that Gram-Schmidt orthogonalisation
- * needs, Section 1.2).  TSG_OP_C on a real type is the same as TSG_OP_T. */
+ * needs, Section 1.2).  TSG_OP_C on a real type is the same as TSG_OP_T.
+ * TSG_OP_N (no transpose) is only meaningful for TSMM's small operand, see
+ * tsg_tsmm_op. */
 typedef enum {
     TSG_OP_T = 0,
-    TSG_OP_C = 1
+    TSG_OP_C = 1,
+    TSG_OP_N = 2
 } tsg_op;
 
 typedef enum {
@@ -93,11 +96,12 @@ typedef enum {
  * when K == 0 (A, B).  C must not overlap A or B.
  *
  * Arithmetic: binary64 fused multiply-adds for TSG_R64 / TSG_C128.  For the
- * precision form (TSG_R32 / TSG_C64) every product of two binary32 numbers is
- * formed exactly, short runs of them are summed in binary32 with an
- * error-free transformation (a compensated sum), and every run is folded
- * into binary64 partial sums; the reduction across threads and blocks is in
- * binary64.
+ * precision form (TSG_R32 / TSG_C64) the binary32 values are widened exactly
+ * to binary64; a product of two of them has at most 48 significant bits and
+ * is therefore formed exactly (error-free, as a compensated product would
+ * make it), and the products are accumulated in binary64, as is the
+ * reduction across threads and blocks.  The result differs from the binary64
+ * sum of the stored binary32 values only by binary64 rounding.
  */
 tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
                        const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -123,6 +127,21 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
 tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N,
                     const void *A, int64_t lda, const void *C, int64_t ldc,
                     void *B, int64_t ldb, double alpha, double beta, void *stream);
+
+/*
+ * TSMM with an operation on the small matrix:
+ *   B(k, n) = alpha * sum_m opA(A(k, m)) * opC(C)(m, n) + beta * B(k, n)
+ * opC = TSG_OP_N: opC(C)(m, n) = C[m * ldc + n]   (C stored M x N, ldc >= N);
+ * opC = TSG_OP_T: opC(C)(m, n) = C[n * ldc + m]   (C stored N x M, ldc >= M);
+ * opC = TSG_OP_C: conj(C[n * ldc + m])            (complex; real types as T).
+ * The transposed forms are what the gradients of TSMTTSM need
+ * (dA = B dC^T, dA = B dC^H); the small matrix is transposed while it is
+ * staged on chip, so no copy of it is made.  Otherwise as tsg_tsmm, which
+ * equals tsg_tsmm_op with TSG_OP_N.
+ */
+tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32_t M, int32_t N,
+                       const void *A, int64_t lda, const void *C, int64_t ldc,
+                       void *B, int64_t ldb, double alpha, double beta, void *stream);
 
 /* Make sure the workspace of (current device, stream) can serve a TSMTTSM of
  * this shape without allocating, e.g. before capturing the stream into a

@@ -10,4 +10,7 @@ def __getattr__(name):
     if name in ("tsmttsm", "tsmm", "kernel_name"):
         from . import api
         return getattr(api, name)
+    if name == "TSMTTSM":
+        from . import autograd
+        return autograd.TSMTTSM
     raise AttributeError(name)

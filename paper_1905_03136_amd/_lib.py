@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TSG_LIBRARY", os.path.join(HERE, "libtsgemm.so"))
 
 TSG_R64, TSG_C128, TSG_R32, TSG_C64 = 0, 1, 2, 3
-TSG_OP_T, TSG_OP_C = 0, 1
+TSG_OP_T, TSG_OP_C, TSG_OP_N = 0, 1, 2
 TSG_OK, TSG_E_ARG, TSG_E_UNSUPPORTED, TSG_E_NOMEM, TSG_E_HIP, TSG_E_CAPTURE = range(6)
 STATUS_NAMES = {0: "TSG_OK", 1: "TSG_E_ARG", 2: "TSG_E_UNSUPPORTED", 3: "TSG_E_NOMEM", 4: "TSG_E_HIP",
                 5: "TSG_E_CAPTURE"}
@@ -21,6 +21,7 @@ _i32, _i64, _vp, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ct
 PROTOTYPES = {
     "tsg_tsmttsm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "tsg_tsmm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
+    "tsg_tsmm_op": (_i32, [_i32, _i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
     "tsg_reserve": (_i32, [_i32, _i64, _i32, _i32, _vp]),
     "tsg_workspace_size": (_sz, [_i32, _i64, _i32, _i32]),
     "tsg_init": (_i32, [_i32]),
@@ -76,6 +77,10 @@ def tsg_tsmttsm(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream):
 
 def tsg_tsmm(dt, conjA, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream):
     return lib().tsg_tsmm(dt, conjA, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream)
+
+
+def tsg_tsmm_op(dt, conjA, opC, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream):
+    return lib().tsg_tsmm_op(dt, conjA, opC, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream)
 
 
 def tsg_reserve(dt, K, M, N, stream):

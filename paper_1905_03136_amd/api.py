@@ -52,9 +52,11 @@ def tsmttsm(A, B, op="T", out=None):
     return out
 
 
-def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False):
-    """B = alpha * op(A) C + beta * out for tall A (K x M) and small C (M x N).
+def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False, opC="N"):
+    """B = alpha * op(A) opC(C) + beta * out for tall A (K x M).
 
+    opC: 'N' uses C (M x N); 'T' uses C^T and 'C' uses C^H of a stored
+    (N x M) C -- the small matrix is transposed on chip, not copied.
     Writes into ``out`` (K x N, A's dtype) when given, else into a new tensor
     (beta must then be 0).  C is float64 / complex128 for every storage type.
     """
@@ -62,20 +64,23 @@ def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False):
         raise TypeError("unsupported dtype combination %s, %s" % (A.dtype, C.dtype))
     if A.device != C.device or A.device.type != "cuda":
         raise ValueError("A and C must be on the same GPU")
+    if opC not in ("N", "T", "C"):
+        raise ValueError("opC must be 'N', 'T' or 'C'")
     K, M = A.shape
-    if C.shape[0] != M:
-        raise ValueError("C must have M rows")
-    N = C.shape[1]
+    Mc, N = (C.shape[0], C.shape[1]) if opC == "N" else (C.shape[1], C.shape[0])
+    if Mc != M:
+        raise ValueError("op(C) must have M rows")
     if out is None:
         if beta != 0.0:
             raise ValueError("beta != 0 needs out")
         out = torch.empty((K, N), dtype=A.dtype, device=A.device)
     elif out.shape != (K, N) or out.dtype != A.dtype or out.device != A.device:
         raise ValueError("out must be a (K, N) %s tensor on %s" % (A.dtype, A.device))
+    op = {"N": _lib.TSG_OP_N, "T": _lib.TSG_OP_T, "C": _lib.TSG_OP_C}[opC]
     with torch.cuda.device(A.device):
-        _lib.check(_lib.tsg_tsmm(_DT[A.dtype], int(bool(conjA)), K, M, N, A.data_ptr(), _ld(A, "A"),
-                                 C.data_ptr(), _ld(C, "C"), out.data_ptr(), _ld(out, "out"),
-                                 float(alpha), float(beta), _stream(A.device)))
+        _lib.check(_lib.tsg_tsmm_op(_DT[A.dtype], int(bool(conjA)), op, K, M, N, A.data_ptr(), _ld(A, "A"),
+                                    C.data_ptr(), _ld(C, "C"), out.data_ptr(), _ld(out, "out"),
+                                    float(alpha), float(beta), _stream(A.device)))
     return out
 
 

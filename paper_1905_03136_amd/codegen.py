@@ -17,12 +17,21 @@ import json
 import math
 import os
 
-DTYPES = {"r64": (0, False), "c128": (1, True)}
+# storage types of the tall matrices: (ABI id, complex).  r32 / c64 are the
+# precision form (binary32 storage, binary64 arithmetic on widened values).
+DTYPES = {"r64": (0, False), "c128": (1, True), "r32": (2, False), "c64": (3, True)}
+F32_DTYPES = ("r32", "c64")
 OPS = {"tsmttsm": 0, "tsmm": 1}
 
 # widths of the plain sweep and the square widths of the target range
 GRADED = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8), (8, 32)]
 SQUARE_ALL = [(w, w) for w in range(1, 65)]
+# pre-generated widths of the precision form (others use run-time-width variants)
+PRECISION = GRADED
+
+
+def is_f32(dt):
+    return dt in F32_DTYPES
 
 WPB = 4  # waves per block
 
@@ -50,7 +59,15 @@ def candidates(op, dt, M, N):
     """Every configuration the autotuner times for (op, dt, M, N), pruned by
     a register model (the gfx950 analogue of the paper's register estimate
     2 (T_M T_N + 2 (T_M + T_N) + 8), Section 5.2): FP64 operands live in the
-    256 architectural VGPRs, MFMA accumulators may use the AGPRs."""
+    256 architectural VGPRs, MFMA accumulators may use the AGPRs.  The
+    binary32-storage types use the matrix-core kinds only."""
+    out = _candidates(op, dt, M, N)
+    if is_f32(dt):
+        out = [c for c in out if c["kind"] != "valu" and not c.get("VA")]
+    return out
+
+
+def _candidates(op, dt, M, N):
     cw = 2 if DTYPES[dt][1] else 1
     cplx = DTYPES[dt][1]
     out = []
@@ -129,7 +146,7 @@ def default_config(op, dt, M, N):
         mb = _ceil(mbt, mw)
         u = max(1, min(4, 8 // ((mb + nb) * cw)))
         return dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)
-    if M * cw <= 2 and N * cw <= 2:
+    if M * cw <= 2 and N * cw <= 2 and not is_f32(dt):
         return dict(kind="valu", MX=M, NX=N, U=4, VA=int(cw == 1 and M % 2 == 0),
                     VB=int(cw == 1 and N % 2 == 0), WPB=WPB)
     if N <= 16 and M <= 16 and _ceil((16 // N) * M, 4) <= 16 and N < 16:
@@ -156,7 +173,7 @@ def generic_variants():
             out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
                             cfg=dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)))
         # TSMM
-        for mx in ((4, 8) if not cplx else (4,)):
+        for mx in (() if is_f32(dt) else (4, 8) if not cplx else (4,)):
             out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=mx,
                             cfg=dict(kind="valu", MX=mx, NX=mx, U=2, VA=0, VB=0, WPB=WPB)))
         for ms in (4, 8, 16):
@@ -175,6 +192,8 @@ def tuning_variants(widths):
     for op in OPS:
         for dt in DTYPES:
             for (M, N) in widths:
+                if is_f32(dt) and (M, N) not in PRECISION:
+                    continue
                 for c in candidates(op, dt, M, N):
                     v = dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=c)
                     name = variant_name(v)
@@ -198,6 +217,8 @@ def exact_variants(widths, tuned=None):
     for op in OPS:
         for dt in DTYPES:
             for (M, N) in widths:
+                if is_f32(dt) and (M, N) not in PRECISION:
+                    continue
                 cfg = tuned.get((op, dt, M, N)) or default_config(op, dt, M, N)
                 out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=cfg))
     return out
@@ -231,21 +252,23 @@ def _template(v):
     cplx = "true" if DTYPES[v["dt"]][1] else "false"
     M, N = v["M"], v["N"]
     nbuf = c.get("NBUF", 2)
+    f32 = "true" if is_f32(v["dt"]) else "false"
     if c["kind"] == "packed":
-        return "tsg::%s_packed<%d, %d, %d, %s, %d, %d>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf)
+        return "tsg::%s_packed<%d, %d, %d, %s, %d, %d, %s>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf, f32)
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
                 M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
                 "true" if c["VB"] else "false", c["WPB"])
-        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d>" % (
-            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1))
+        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), f32)
     if c["kind"] == "valu":
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d>" % (
-        M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false", c.get("OCC", 1))
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s>" % (
+        M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false",
+        c.get("OCC", 1), f32)
 
 
 def rows_per_tile(v):
@@ -265,7 +288,7 @@ def _launcher(v, fn):
         args = "p.K, p.M, p.N, p.A, p.lda, p.X, p.ldx, static_cast<double*>(p.Y), p.ldy, p.ws, p.conj"
     else:
         args = ("p.K, p.M, p.N, p.A, p.lda, static_cast<const double*>(p.X), p.ldx, p.Y, p.ldy, "
-                "p.alpha, p.beta, p.conj")
+                "p.alpha, p.beta, p.conj, p.opc")
     return ("void %s(const tsg::Launch& p)\n{\n"
             "    hipLaunchKernelGGL((%s), dim3(p.grid), dim3(%d), 0, p.stream, %s);\n}\n"
             "const void* %s() { return reinterpret_cast<const void*>(&%s); }\n"

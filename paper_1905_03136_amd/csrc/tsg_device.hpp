@@ -35,6 +35,61 @@ __device__ __forceinline__ dbl2 ld_stream2(const double* p)
     return __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p));
 }
 
+// ---------------------------------------------------- binary32 storage
+// The precision form stores the tall matrices in binary32 (complex: two
+// binary32).  Loads widen to binary64 exactly; a product of two widened
+// binary32 numbers has at most 48 significant bits, so it is exact in
+// binary64 and the matrix cores accumulate it in binary64.  Stores round the
+// binary64 result once to binary32.
+struct zf {
+    float re, im;
+};
+typedef float flt2 __attribute__((ext_vector_type(2)));
+
+template <bool CPLX, bool F32>
+struct storage;
+template <>
+struct storage<false, false> { typedef double type; };
+template <>
+struct storage<true, false> { typedef zd type; };
+template <>
+struct storage<false, true> { typedef float type; };
+template <>
+struct storage<true, true> { typedef zf type; };
+
+__device__ __forceinline__ double ld_stream(const float* p) { return (double)__builtin_nontemporal_load(p); }
+__device__ __forceinline__ zd ld_stream(const zf* p)
+{
+    const flt2 v = __builtin_nontemporal_load(reinterpret_cast<const flt2*>(p));
+    return zd{(double)v.x, (double)v.y};
+}
+
+// plain (cached) reads, e.g. of the old B when beta != 0
+__device__ __forceinline__ double ld_plain(const double* p) { return *p; }
+__device__ __forceinline__ double ld_plain(const float* p) { return (double)*p; }
+__device__ __forceinline__ zd ld_plain(const zd* p)
+{
+    const dbl2 v = *reinterpret_cast<const dbl2*>(p);
+    return zd{v.x, v.y};
+}
+__device__ __forceinline__ zd ld_plain(const zf* p)
+{
+    const flt2 v = *reinterpret_cast<const flt2*>(p);
+    return zd{(double)v.x, (double)v.y};
+}
+
+// streaming stores of a binary64 result into the storage type
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(float* p, double v) { __builtin_nontemporal_store((float)v, p); }
+__device__ __forceinline__ void st_stream(zd* p, zd v)
+{
+    __builtin_nontemporal_store(dbl2{v.re, v.im}, reinterpret_cast<dbl2*>(p));
+}
+__device__ __forceinline__ void st_stream(zf* p, zd v)
+{
+    __builtin_nontemporal_store(flt2{(float)v.re, (float)v.im}, reinterpret_cast<flt2*>(p));
+}
+
 __device__ __forceinline__ double keep(bool ok, double v) { return ok ? v : 0.0; }
 __device__ __forceinline__ zd keep(bool ok, zd v) { return ok ? v : zd{0.0, 0.0}; }
 
@@ -110,11 +165,10 @@ __device__ __forceinline__ void pipeline(int64_t t0, int64_t ntiles, int64_t G, 
 }
 
 // Cached load, for operands that several waves of a block read.
-__device__ __forceinline__ double ld_shared(const double* p) { return *p; }
-__device__ __forceinline__ zd ld_shared(const zd* p)
+template <class S>
+__device__ __forceinline__ auto ld_shared(const S* p)
 {
-    const dbl2 v = *reinterpret_cast<const dbl2*>(p);
-    return zd{v.x, v.y};
+    return ld_plain(p);
 }
 
 // -------------------------------------------------- wave reduction (fixed tree)

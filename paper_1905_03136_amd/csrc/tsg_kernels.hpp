@@ -29,6 +29,14 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Element (m, n) of TSMM's small operand op(C): opc 0 reads C(m, n) = C[m ldc + n];
+// opc 1 (transpose) and 2 (conjugate transpose, the caller negates the
+// imaginary part) read C[n ldc + m] of a stored N x M matrix.
+__device__ __forceinline__ int64_t small_index(int m, int n, int64_t ldc, int opc)
+{
+    return opc ? (int64_t)n * ldc + m : (int64_t)m * ldc + n;
+}
+
 // ============================================================================
 // TSMTTSM on the matrix cores.
 //
@@ -55,13 +63,15 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
 // Output layout of the 16x16 FP64 accumulator (checked on gfx950 with an
 // in-bounds probe): lane l, element r holds D(l / 16 + 4 r, l % 16).
 // ============================================================================
-template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1>
+template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1,
+          bool F32 = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
              double* __restrict__ ws, int conj)
 {
     using T = elem_t<CPLX>;
+    using S = typename storage<CPLX, F32>::type;  // storage type; loads widen S -> T
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RG = WPB / MW;
     constexpr int RT = 4 * U * RG;
@@ -69,8 +79,8 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
     static_assert(WPB % MW == 0, "waves must split evenly");
     __shared__ double part[EMAX];
 
-    const T* __restrict__ A = static_cast<const T*>(Av);
-    const T* __restrict__ B = static_cast<const T*>(Bv);
+    const S* __restrict__ A = static_cast<const S*>(Av);
+    const S* __restrict__ B = static_cast<const S*>(Bv);
     const int M = MC ? MC : Mr;
     const int N = NC ? NC : Nr;
     const int lane = threadIdx.x & (kWave - 1);
@@ -116,8 +126,8 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             const int64_t row = t * RT + (int64_t)(rg * U + u) * 4 + lr;
             const bool ok = row < K;
             const int64_t rc = ok ? row : K - 1;
-            const T* ar = A + rc * lda;
-            const T* br = B + rc * ldb;
+            const S* ar = A + rc * lda;
+            const S* br = B + rc * ldb;
 #pragma unroll
             for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok && mok[i], ld_stream(ar + moff[i]));
 #pragma unroll
@@ -206,13 +216,14 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // throughput for the low arithmetic intensity of these widths (Eq. 1: M/8
 // flop per byte), so the unused products cost no time.
 // ============================================================================
-template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF>
+template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF, bool F32 = false>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
                double* __restrict__ ws, int conj)
 {
     using T = elem_t<CPLX>;
+    using S = typename storage<CPLX, F32>::type;  // storage type; loads widen S -> T
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int MX = MC ? MC : 16;
     constexpr int NX = NC ? NC : 16;
@@ -225,8 +236,8 @@ tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t l
     __shared__ double part[WPB * 16 * 16 * CW];
     __shared__ double fin[MX * NX * CW];
 
-    const T* __restrict__ A = static_cast<const T*>(Av);
-    const T* __restrict__ B = static_cast<const T*>(Bv);
+    const S* __restrict__ A = static_cast<const S*>(Av);
+    const S* __restrict__ B = static_cast<const S*>(Bv);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int q = lane >> 4;
@@ -454,7 +465,7 @@ template <int MC, int NC, int MX, int NX, int U, bool CPLX, bool VA, bool VB, in
 __global__ void __launch_bounds__(WPB * kWave)
 tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
-          double alpha, double beta, int conj)
+          double alpha, double beta, int conj, int opc)
 {
     using T = elem_t<CPLX>;
     constexpr int RT = kWave * U * WPB;
@@ -501,7 +512,8 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 #pragma unroll
             for (int i = 0; i < MX; ++i) {
                 if ((MC || i < M) && (NC || j < N)) {
-                    const T c = Cz[(int64_t)i * ldc + j];
+                    T c = Cz[small_index(i, j, ldc, opc)];
+                    if constexpr (CPLX) c.im = opc == 2 ? -c.im : c.im;
                     if constexpr (!CPLX) {
                         s = __builtin_fma(a[i], c, s);
                     } else {
@@ -575,25 +587,27 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // rows l/16 + 4r (r < 4) of column l%16 of each 16 x 16 output block: sixteen
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
-template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1>
+template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1,
+          bool F32 = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
-          double alpha, double beta, int conj)
+          double alpha, double beta, int conj, int opc)
 {
     // VA: A is read with 16-byte loads, A(row, 8t + 2q .. 8t + 2q + 1) for the
     // lane of k-slot q, which serve the steps s = 2t (even column) and 2t + 1
     // (odd column); the contraction order over m is permuted accordingly,
     // m(s, q) = 8 (s / 2) + 2 q + s % 2, and C is staged in the same order.
-    static_assert(!VA || (!CPLX && MS % 2 == 0), "paired A loads: real data, M a multiple of 8");
+    static_assert(!VA || (!CPLX && !F32 && MS % 2 == 0), "paired A loads: binary64 real data, M a multiple of 8");
     using T = elem_t<CPLX>;
+    using S = typename storage<CPLX, F32>::type;  // storage type of A and B
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RT = 16 * U * WPB;
     constexpr int NFRAG = MS * NB * kWave;
     __shared__ double cf[NFRAG * CW];
 
-    const T* __restrict__ A = static_cast<const T*>(Av);
-    T* __restrict__ B = static_cast<T*>(Bv);
+    const S* __restrict__ A = static_cast<const S*>(Av);
+    S* __restrict__ B = static_cast<S*>(Bv);
     const int M = MC ? MC : Mr;
     const int N = NC ? NC : Nr;
     const int lane = threadIdx.x & (kWave - 1);
@@ -611,10 +625,11 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         const int n = 16 * j + (l & 15);
         const bool ok = m < M && n < N;
         if constexpr (CPLX) {
-            cf[idx] = ok ? Cm[2 * ((int64_t)m * ldc + n)] : 0.0;
-            cf[NFRAG + idx] = ok ? Cm[2 * ((int64_t)m * ldc + n) + 1] : 0.0;
+            const int64_t ci = small_index(m, n, ldc, opc);
+            cf[idx] = ok ? Cm[2 * ci] : 0.0;
+            cf[NFRAG + idx] = ok ? (opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0;
         } else {
-            cf[idx] = ok ? Cm[(int64_t)m * ldc + n] : 0.0;
+            cf[idx] = ok ? Cm[small_index(m, n, ldc, opc)] : 0.0;
         }
     }
     __syncthreads();
@@ -637,7 +652,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lc;
             const int64_t rc = row < K ? row : K - 1;
-            const T* ar = A + rc * lda;
+            const S* ar = A + rc * lda;
             if constexpr (VA) {
 #pragma unroll
                 for (int s = 0; s < MS; s += 2) {
@@ -711,18 +726,18 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                     for (int r = 0; r < 4; ++r) {
                         const int64_t row = rbase + 4 * r;
                         if (full || row < K) {
-                            T* p = B + row * ldb + n;
+                            S* p = B + row * ldb + n;
                             if constexpr (!CPLX) {
                                 double v = alpha * acc[u][j][r];
-                                if (read_b) v = __builtin_fma(beta, *p, v);
-                                __builtin_nontemporal_store(v, p);
+                                if (read_b) v = __builtin_fma(beta, ld_plain(p), v);
+                                st_stream(p, v);
                             } else {
-                                dbl2 v = dbl2{alpha * acc[u][j][r], alpha * acci[u][j][r]};
+                                zd v = zd{alpha * acc[u][j][r], alpha * acci[u][j][r]};
                                 if (read_b) {
-                                    const zd o = *p;
-                                    v = dbl2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
+                                    const zd o = ld_plain(p);
+                                    v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
                                 }
-                                __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p));
+                                st_stream(p, v);
                             }
                         }
                     }
@@ -746,14 +761,15 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // otherwise (a block-diagonal copy of C, staged once per block in LDS in
 // fragment order).  A lane's A operand for pair q is A(k0 + i P + h, m).
 // ============================================================================
-template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF>
+template <int MC, int NC, int U, bool CPLX, int WPB, int NBUF, bool F32 = false>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
-            double alpha, double beta, int conj)
+            double alpha, double beta, int conj, int opc)
 {
     static_assert(MC > 0 && NC > 0 && NC <= 16, "row-packed TSMM needs compile-time widths, N <= 16");
     using T = elem_t<CPLX>;
+    using ST = typename storage<CPLX, F32>::type;  // storage type of A and B
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int P = 16 / NC;
     constexpr int QN = P * MC;             // contraction pairs (h, m)
@@ -763,8 +779,8 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int NFRAG = S * kWave;
     __shared__ double cf[NFRAG * CW];
 
-    const T* __restrict__ A = static_cast<const T*>(Av);
-    T* __restrict__ B = static_cast<T*>(Bv);
+    const ST* __restrict__ A = static_cast<const ST*>(Av);
+    ST* __restrict__ B = static_cast<ST*>(Bv);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int lr = lane >> 4;
@@ -780,10 +796,11 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         const int hj = j / NC, n = j - hj * NC;
         const bool ok = qq < QN && hj < P && hq == hj;
         if constexpr (CPLX) {
-            cf[idx] = ok ? Cm[2 * ((int64_t)m * ldc + n)] : 0.0;
-            cf[NFRAG + idx] = ok ? Cm[2 * ((int64_t)m * ldc + n) + 1] : 0.0;
+            const int64_t ci = small_index(m, n, ldc, opc);
+            cf[idx] = ok ? Cm[2 * ci] : 0.0;
+            cf[NFRAG + idx] = ok ? (opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0;
         } else {
-            cf[idx] = ok ? Cm[(int64_t)m * ldc + n] : 0.0;
+            cf[idx] = ok ? Cm[small_index(m, n, ldc, opc)] : 0.0;
         }
     }
     __syncthreads();
@@ -860,18 +877,18 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = r0 + (int64_t)(lr + 4 * r) * P;
                     if (full || row < K) {
-                        T* p = B + row * ldb + nj;
+                        ST* p = B + row * ldb + nj;
                         if constexpr (!CPLX) {
                             double v = alpha * acc[u][r];
-                            if (read_b) v = __builtin_fma(beta, *p, v);
-                            __builtin_nontemporal_store(v, p);
+                            if (read_b) v = __builtin_fma(beta, ld_plain(p), v);
+                            st_stream(p, v);
                         } else {
-                            dbl2 v = dbl2{alpha * acc[u][r], alpha * acci[u][r]};
+                            zd v = zd{alpha * acc[u][r], alpha * acci[u][r]};
                             if (read_b) {
-                                const zd o = *p;
-                                v = dbl2{__builtin_fma(beta, o.re, v.x), __builtin_fma(beta, o.im, v.y)};
+                                const zd o = ld_plain(p);
+                                v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
                             }
-                            __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(p));
+                            st_stream(p, v);
                         }
                     }
                 }

@@ -15,6 +15,7 @@ struct Launch {
     int64_t K;
     int M, N;
     int conj;
+    int opc;  // TSMM small operand: 0 C, 1 C^T, 2 C^H
     const void* A;
     int64_t lda;
     const void* X;

@@ -235,8 +235,6 @@ tsg_status validate(tsg_dtype dt, int64_t K, int32_t M, int32_t N, const void* A
             return fail(TSG_E_ARG, "A and B must be aligned to %zu bytes", es);
         if (X && !aligned(X, is_complex(dt) ? 16 : 8)) return fail(TSG_E_ARG, "C must be aligned to its element size");
     }
-    if (dt == TSG_R32 || dt == TSG_C64)
-        return fail(TSG_E_UNSUPPORTED, "the binary32 storage types are not built into this library");
     return TSG_OK;
 }
 
@@ -316,11 +314,16 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
     return TSG_OK;
 }
 
-tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
-                    const void* C, int64_t ldc, void* B, int64_t ldb, double alpha, double beta, void* stream)
+tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32_t M, int32_t N, const void* A,
+                       int64_t lda, const void* C, int64_t ldc, void* B, int64_t ldb, double alpha, double beta,
+                       void* stream)
 {
     g_err.clear();
-    tsg_status s = validate(dt, K, M, N, A, lda, C, ldc, B, ldb, tsg::OP_TSMM);
+    if (opC != TSG_OP_N && opC != TSG_OP_T && opC != TSG_OP_C) return fail(TSG_E_ARG, "unknown opC %d", (int)opC);
+    if (opC != TSG_OP_N && M >= 1 && ldc < M)
+        return fail(TSG_E_ARG, "ldc = %lld < M = %d for a transposed small matrix", (long long)ldc, M);
+    const int64_t ldc_check = opC == TSG_OP_N ? ldc : (ldc > N ? ldc : (int64_t)N);
+    tsg_status s = validate(dt, K, M, N, A, lda, C, ldc_check, B, ldb, tsg::OP_TSMM);
     if (s != TSG_OK) return s;
     if (K == 0) return TSG_OK;
     int dev;
@@ -337,6 +340,7 @@ tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N
     p.M = M;
     p.N = N;
     p.conj = (conjA && is_complex(dt)) ? 1 : 0;
+    p.opc = opC == TSG_OP_N ? 0 : ((opC == TSG_OP_C && is_complex(dt)) ? 2 : 1);
     p.A = A;
     p.lda = lda;
     p.X = C;
@@ -349,6 +353,12 @@ tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
     return TSG_OK;
+}
+
+tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
+                    const void* C, int64_t ldc, void* B, int64_t ldb, double alpha, double beta, void* stream)
+{
+    return tsg_tsmm_op(dt, conjA, TSG_OP_N, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream);
 }
 
 size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N)

@@ -52,9 +52,11 @@ def cmd_build(args):
     build.build(variants=variants, lib_path=TUNE_LIB, tag="_tune")
 
 
-def _algorithmic(op, cplx, K, M, N):
-    s = 16 if cplx else 8
-    return s * (K * M + K * N + M * N), (8 if cplx else 2) * M * N * K
+def _algorithmic(op, cplx, K, M, N, real_bytes=8):
+    """Eq. 1 bytes (tall matrices in the storage type, C in binary64) and flops."""
+    s = (2 if cplx else 1) * real_bytes
+    c = 16 if cplx else 8
+    return s * (K * M + K * N) + c * M * N, (8 if cplx else 2) * M * N * K
 
 
 def cmd_run(args):
@@ -92,26 +94,33 @@ def cmd_run(args):
         pools[cplx] = t
     db = open(args.db, "a")
     t_start = time.time()
+    dtypes = set(args.dtypes.split(",")) if args.dtypes else None
     for key in sorted(groups, key=lambda k: (k[0], k[1], k[2] * k[3])):
         op, dt, M, N = key
-        cplx = dt == "c128"
+        if dtypes and dt not in dtypes:
+            continue
+        cplx = dt in ("c128", "c64")
+        f32 = codegen.is_f32(dt)
         cw = 2 if cplx else 1
-        tdt = torch.complex128 if cplx else torch.float64
+        tdt = torch.complex128 if cplx else torch.float64            # small matrix C
+        sdt = {"r64": torch.float64, "c128": torch.complex128,
+               "r32": torch.float32, "c64": torch.complex64}[dt]      # storage of A, B
         cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
         if not cands:
             continue
         # integer-valued reference problem (exact in binary64): all candidates must agree bit for bit
         kc = 4099
-        Ai = torch.from_numpy(inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)).to(dev)
-        Bi = torch.from_numpy(inputs.host_integers(kc, N, 7, inputs.STREAM_B, cplx)).to(dev)
+        Ai = torch.from_numpy(inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)).to(dev).to(sdt)
+        Bi = torch.from_numpy(inputs.host_integers(kc, N, 7, inputs.STREAM_B, cplx)).to(dev).to(sdt)
         Xi = torch.from_numpy(inputs.host_integers(M, N, 7, inputs.STREAM_C, cplx)).to(dev)
-        # buffer sets for timing
+        # buffer sets for timing (pool reinterpreted as binary32 for the precision form)
+        pool = pools[cplx].view(torch.float32) if f32 else pools[cplx]
         ws_elems = K * (M + N) * cw
-        ws_bytes = ws_elems * 8
-        R = max(1, min(int(math.ceil((1 << 30) / ws_bytes)), pool_elems * cw // ws_elems))
+        ws_bytes = ws_elems * pool.element_size()
+        R = max(1, min(int(math.ceil((1 << 30) / ws_bytes)), pool.numel() // ws_elems))
         sets = []
         for r in range(R):
-            base = pools[cplx][r * ws_elems:(r + 1) * ws_elems]
+            base = pool[r * ws_elems:(r + 1) * ws_elems]
             a = base[:K * M * cw]
             b = base[K * M * cw:]
             if cplx:
@@ -123,7 +132,7 @@ def cmd_run(args):
             sets.append((a, b))
         Xs = inputs.device_uniform(M, N, 3, inputs.STREAM_C, cplx, dev)
         Cout = torch.empty((M, N), dtype=tdt, device=dev)
-        byts, flops = _algorithmic(op, cplx, K, M, N)
+        byts, flops = _algorithmic(op, cplx, K, M, N, 4 if f32 else 8)
         ref = None
         for v in cands:
             name = codegen.variant_name(v)
@@ -168,12 +177,18 @@ def cmd_run(args):
                 flush=True)
     db.close()
     print("[tune] done in %.0f s" % (time.time() - t_start), flush=True)
-    write_table(args.db, args.out)
+    write_table(args.db, args.out, args.merge)
 
 
-def write_table(db_path, out_path):
-    """Fastest correct configuration per (op, dtype, M, N) from the database."""
+def write_table(db_path, out_path, merge=None):
+    """Fastest correct configuration per (op, dtype, M, N) from the database;
+    entries of an existing table ``merge`` that the database does not cover
+    are kept."""
     best = {}
+    if merge and os.path.exists(merge):
+        with open(merge) as f:
+            for e in json.load(f).get("entries", []):
+                best[(e["op"], e["dt"], e["M"], e["N"])] = dict(e, _kept=True)
     with open(db_path) as f:
         for line in f:
             try:
@@ -183,7 +198,7 @@ def write_table(db_path, out_path):
             if not r.get("ok") or "us" not in r:
                 continue
             key = (r["op"], r["dt"], r["M"], r["N"])
-            if key not in best or r["us"] < best[key]["us"]:
+            if key not in best or best[key].get("_kept") or r["us"] < best[key]["us"]:
                 best[key] = r
     entries = [dict(op=k[0], dt=k[1], M=k[2], N=k[3], cfg=r["cfg"], name=r["name"], us=r["us"],
                     GBps=r["GBps"], roof_frac=r["roof_frac"], K=r["K"])
@@ -201,21 +216,24 @@ def main(argv=None):
     b.add_argument("--widths", default="graded")
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
+    r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")
     r.add_argument("--K", type=int, default=1 << 24)
     r.add_argument("--db", default="gpurun_out/tune_db.jsonl")
     r.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
     r.add_argument("--reps", type=int, default=5)
     r.add_argument("--warmup", type=int, default=2)
+    r.add_argument("--merge", default="", help="keep the entries of this table the run does not cover")
     t = sub.add_parser("table")
     t.add_argument("--db", default="gpurun_out/tune_db.jsonl")
     t.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
+    t.add_argument("--merge", default="")
     a = ap.parse_args(argv)
     if a.cmd == "build":
         cmd_build(a)
     elif a.cmd == "run":
         cmd_run(a)
     else:
-        write_table(a.db, a.out)
+        write_table(a.db, a.out, a.merge)
 
 
 if __name__ == "__main__":

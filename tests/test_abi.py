@@ -100,7 +100,13 @@ def test_kernel_names_cover_all_widths(lib):
     assert _lib.tsg_kernel_name(0, 0, 0, 65, 1) == ""
 
 
-def test_precision_dtypes_reported_unsupported_until_built(lib):
-    # binary32 storage is declared in the ABI; the status tells whether it is built
-    st = _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A, 4, A, 4, A, 4, None)
-    assert st in (_lib.TSG_E_UNSUPPORTED, _lib.TSG_E_HIP)
+def test_precision_dtypes_validated(lib):
+    # binary32 storage: 4-byte (real) / 8-byte (complex) alignment of A and B, C stays binary64
+    assert _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A + 4, 4, A, 4, A, 4, None) != _lib.TSG_E_ARG
+    assert _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A + 2, 4, A, 4, A, 4, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_tsmttsm(_lib.TSG_C64, 0, 10, 4, 4, A + 4, 4, A, 4, A, 4, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A, 4, A, 4, A + 4, 4, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_tsmm_op(_lib.TSG_R64, 0, 7, 10, 4, 4, A, 4, A, 4, A, 4, 1.0, 0.0, None) == _lib.TSG_E_ARG
+    # a transposed small matrix is stored N x M: ldc >= M
+    assert _lib.tsg_tsmm_op(_lib.TSG_R64, 0, _lib.TSG_OP_T, 10, 6, 4, A, 6, A, 5, A, 4, 1.0, 0.0, None) \
+        == _lib.TSG_E_ARG

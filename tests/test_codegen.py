@@ -29,8 +29,18 @@ def test_names_unique_and_graded_widths_exact():
     exact = {(x["op"], x["dt"], x["M"], x["N"]) for x in v if x["M"]}
     for op in codegen.OPS:
         for dt in codegen.DTYPES:
-            for M, N in codegen.GRADED + codegen.SQUARE_ALL:
+            widths = codegen.PRECISION if codegen.is_f32(dt) else codegen.GRADED + codegen.SQUARE_ALL
+            for M, N in widths:
                 assert (op, dt, M, N) in exact
+
+
+def test_binary32_storage_uses_matrix_core_kinds_only():
+    for op in codegen.OPS:
+        for dt in codegen.F32_DTYPES:
+            for M, N in codegen.PRECISION + [(3, 3), (40, 5)]:
+                assert all(c["kind"] != "valu" and not c.get("VA") for c in codegen.candidates(op, dt, M, N))
+                assert codegen.default_config(op, dt, M, N)["kind"] != "valu"
+    assert all(v["cfg"]["kind"] != "valu" for v in codegen.generic_variants() if codegen.is_f32(v["dt"]))
 
 
 def test_default_configs_respect_register_budget():
