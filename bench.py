@@ -13,6 +13,7 @@ CPU oracle timed on a bounded sample of the same sweep.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import glob
 import json
 import os
 import platform
@@ -125,6 +126,79 @@ def precision_form(torch, api, inputs, dev, K=1 << 25, widths=(8, 32, 64)):
                     "error against the binary64 oracle on the stored values is at the binary64 level "
                     "(tests check <= 1e-12 for TSMTTSM, one binary32 rounding for TSMM outputs)",
             "widths": out}
+
+
+def batched_form(torch, api, inputs, dev, reps=5):
+    """64 block-orthogonalisation steps (C_i = V_i^T W_i, W_i -= V_i C_i),
+    K_i log-uniform in [2^16, 2^22], M_i in {4,8,16,32,64}, N_i in {1,4,8,16}:
+    one persistent launch replayed from its graph, against the same work as
+    128 separate library calls (64 TSMTTSM + 64 TSMM updates) on one stream,
+    and against those calls captured in one graph.  V_i is uniform(-1, 1)
+    scaled by sqrt(3 / K_i) (columns of unit expected norm, nearly orthogonal)
+    so that repeated in-place steps keep W bounded; the time does not depend
+    on the values."""
+    from paper_1905_03136_amd import _lib
+    shapes = inputs.batched_instances(64, seed=0)
+    pairs, Cs = [], []
+    for i, (K, M, N) in enumerate(shapes):
+        V = inputs.device_uniform(K, M, 100 + i, inputs.STREAM_V0, False, dev)
+        V.mul_((3.0 / K) ** 0.5)
+        W = inputs.device_uniform(K, N, 100 + i, inputs.STREAM_W0, False, dev)
+        pairs.append((V, W))
+        Cs.append(torch.empty((M, N), dtype=torch.float64, device=dev))
+    byts = sum(8 * K * (2 * M + 3 * N) for K, M, N in shapes)
+    ideal = sum(8 * K * (M + 2 * N) for K, M, N in shapes)
+    flops = sum(4 * K * M * N for K, M, N in shapes)
+    W0 = [w.clone() for _, w in pairs]
+
+    def separate():
+        for (V, W), C in zip(pairs, Cs):
+            api.tsmttsm(V, W, out=C)
+            api.tsmm(V, C, out=W, alpha=-1.0, beta=1.0)
+
+    plan = api.OrthPlan(pairs)
+    t_persist = time_call(torch, plan.launch, reps=reps, warmup=2)
+    plan.check()
+    t_sep = time_call(torch, separate, reps=reps, warmup=2)
+    # the separate calls captured into one graph (workspaces reserved by the warm-up on the capture stream)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        separate()
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        separate()
+    t_graph = time_call(torch, g.replay, reps=reps, warmup=2)
+    # agreement of the two paths from the same W (different summation orders)
+    for (_, w), w0 in zip(pairs, W0):
+        w.copy_(w0)
+    plan.launch()
+    plan.check()
+    C_p = [c.clone() for c in plan.C]
+    W_p = [w.clone() for _, w in pairs]
+    for (_, w), w0 in zip(pairs, W0):
+        w.copy_(w0)
+    separate()
+    torch.cuda.synchronize()
+    rel_C = max(float((a - b).norm() / b.norm().clamp_min(1e-300)) for a, b in zip(C_p, Cs))
+    rel_W = max(float((a - w).norm() / w.norm().clamp_min(1e-300)) for a, (_, w) in zip(W_p, pairs))
+    plan.close()
+    del g
+    return {"instances": 64, "rows": sum(k for k, _, _ in shapes),
+            "algorithmic_bytes": byts, "cache_ideal_bytes": ideal, "flops": flops,
+            "us_persistent_graph": round(t_persist * 1e6, 1), "us_128_launches": round(t_sep * 1e6, 1),
+            "us_128_launches_graph": round(t_graph * 1e6, 1),
+            "speedup_vs_launches": round(t_sep / t_persist, 3),
+            "speedup_vs_launch_graph": round(t_graph / t_persist, 3),
+            "GBps_persistent": round(byts / t_persist / 1e9, 1),
+            "roof_frac_persistent": round(byts / t_persist / HBM_PEAK, 4),
+            "GBps_persistent_cache_ideal": round(ideal / t_persist / 1e9, 1),
+            "GBps_128_launches": round(byts / t_sep / 1e9, 1),
+            "max_rel_diff_C": rel_C, "max_rel_diff_W": rel_W,
+            "note": "bytes = sum 8 K (2M + 3N) (phase 1 reads V and W; phase 2 reads V and W and writes W); "
+                    "cache-ideal sum 8 K (M + 2N); rel diffs are normwise between the persistent and the "
+                    "separate-launch results from the same inputs"}
 
 
 def cpu_baseline(K_sample):
@@ -249,9 +323,20 @@ def main():
     else:
         roof = {"bound": "mfma", "achieved": round(dc["flops"] / dt / 1e12, 2), "peak": FP64_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": round(dc["flops"] / dt / FP64_PEAK, 4)}
-    roof.update({"kernel": d["kernel"], "avg_us": d["us"], "traffic": None,
+    from paper_1905_03136_amd import codegen, profile_summary
+    src_hash = profile_summary.source_hash()
+    symbol = codegen.kernel_symbol(d["kernel"])
+    roof.update({"kernel": d["kernel"], "kernel_symbol": symbol, "avg_us": d["us"], "bytes": dc["bytes"],
+                 "flops": dc["flops"], "traffic": None,
                  "per_launch": "%s %s M=%d N=%d K=%d: %d algorithmic bytes, %d flops" % (
                      d["op"], d["dtype"], d["M"], d["N"], K, dc["bytes"], dc["flops"])})
+    # HBM bytes per launch from the committed counter summary of the same kernel code, if there is one
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        rec = profile_summary.traffic_record(f, symbol, src_hash)
+        if rec:
+            roof["traffic"] = rec["traffic"]
+            roof["traffic_source"] = "profiles/" + os.path.basename(f)
+            break
 
     if not a.no_check:
         # spot check of the timed buffers: one TSMTTSM entry against a direct FP64 dot product
@@ -265,6 +350,7 @@ def main():
         "metric": METRIC, "value": round(step_bytes * a.steps / (t1 - t0) / 1e9, 1), "unit": "GB/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "source_hash": src_hash,
         "data": "synthetic (seeded uniform(-1,1), generated on the device)",
         "config": {"workload": "plain width sweep: TSMTTSM and TSMM, D and Z, K=2^24, "
                                "(M,N) in {(1,1),(2,2),(4,4),(8,8),(16,16),(32,32),(64,64),(32,8),(8,32)}",
@@ -280,6 +366,10 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] precision form (binary32 storage) at K=2^25", file=sys.stderr, flush=True)
         out["precision_form"] = precision_form(torch, api, inputs, dev)
+        torch.cuda.empty_cache()
+        print("[bench] batched form (64 orthogonalisation steps, one persistent launch)", file=sys.stderr,
+              flush=True)
+        out["batched_form"] = batched_form(torch, api, inputs, dev)
     if a.cpu_sample > 0:
         print("[bench] timing the CPU oracle on a %d-row sample" % a.cpu_sample, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)

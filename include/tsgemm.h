@@ -143,6 +143,73 @@ tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32
                        const void *A, int64_t lda, const void *C, int64_t ldc,
                        void *B, int64_t ldb, double alpha, double beta, void *stream);
 
+/* ---- batched block orthogonalisation (one persistent launch) ----
+ * Classical Gram-Schmidt of a block W against an orthonormal basis V needs
+ * both products (Section 1.2): C = V^T W, then W <- W - V C.  The batched form
+ * runs that step for `count` independent instances (real binary64; each with
+ * its own K_i, M_i <= 64, N_i <= 16) in ONE persistent kernel launch.  A
+ * device work queue holds first every instance's K-slab items (TSMTTSM
+ * partial sums), then every row-slab item (the TSMM update); the last slab
+ * item of an instance folds its partials in a fixed order into C_i and marks
+ * the instance ready, and an update item starts once its instance is ready.
+ * Because all first-phase items are queued before any update item, a waiting
+ * update never blocks the work it waits for.  Results are deterministic: the
+ * slab boundaries and every summation order are fixed by the plan, not by
+ * which block takes which item.  C_i is computed in binary64 by matrix-core
+ * products of four rows, summed over the slab's rows, then over slabs in
+ * order; the update is W <- W + V (-C) with the same products.
+ *
+ * Descriptor of instance i (all device pointers, row-major):
+ *   V (K x M, ldv >= M) read only; W (K x N, ldw >= N) updated in place;
+ *   C (M x N, ldc >= N) written with V^T W of the OLD W.  W must not overlap
+ *   V or C, and instances must not overlap each other's W or C. */
+typedef struct {
+    int64_t K;
+    int32_t M, N;
+    const double *V;
+    int64_t ldv;
+    double *W;
+    int64_t ldw;
+    double *C;
+    int64_t ldc;
+} tsg_orth_desc;
+
+typedef struct tsg_orth_plan_t *tsg_orth_plan;
+
+/* Build a plan for `count` >= 1 instances (host array of descriptors, read
+ * only during the call) on the current device: validates them, uploads the
+ * descriptors and the work-item table, allocates the plan's workspace
+ * (partial sums, counters, flags) and captures one launch into a hipGraph on
+ * a private stream.  rows_per_item > 0 fixes the slab height of every
+ * instance; <= 0 picks it per instance (about 2 MiB of input per slab, at
+ * most 256 slabs per instance).  Instances are queued largest first.
+ * Errors: TSG_E_ARG (null plan/descs, count < 1, K_i < 0, M_i or N_i < 1,
+ * ld too small, null or misaligned pointer with K_i > 0, null C_i),
+ * TSG_E_UNSUPPORTED (M_i > 64, N_i > 16, slab height > 2^30), TSG_E_NOMEM,
+ * TSG_E_HIP.  Allocates: never call it while a stream is being captured.
+ * `stream` is unused (reserved). */
+tsg_status tsg_orth_plan_create(tsg_orth_plan *plan, int32_t count, const tsg_orth_desc *descs,
+                                int64_t rows_per_item, void *stream);
+/* Replay the plan's graph on `stream` (a stream of the plan's device;
+ * asynchronous).  Launches of one plan must not overlap: they share its
+ * counters. */
+tsg_status tsg_orth_plan_launch(tsg_orth_plan plan, void *stream);
+/* Launch the persistent kernel directly (no graph) on `stream`; may itself be
+ * captured by the caller.  Same ordering rule as tsg_orth_plan_launch. */
+tsg_status tsg_orth_plan_run(tsg_orth_plan plan, void *stream);
+/* Waits for the device, then returns TSG_OK, or TSG_E_HIP if a wait of an
+ * update item for its instance's C_i ran past the spin limit in a launch since
+ * the last check (the results of that launch are then invalid); clears the
+ * flag. */
+tsg_status tsg_orth_plan_check(tsg_orth_plan plan);
+/* Bound on the sleeps (about 0.2 us each) of one wait; default 2^23.  Stored
+ * on the device, so it applies to graph replays too.  Waits for the device
+ * first.  Meant for tests of the error path: 0 makes every update item give
+ * up at once and raise the flag (its results are then invalid). */
+tsg_status tsg_orth_plan_set_spin_limit(tsg_orth_plan plan, uint32_t limit);
+/* Waits for the device, then frees the plan (null is ignored). */
+void tsg_orth_plan_destroy(tsg_orth_plan plan);
+
 /* Make sure the workspace of (current device, stream) can serve a TSMTTSM of
  * this shape without allocating, e.g. before capturing the stream into a
  * graph.  May allocate (hipMalloc); returns TSG_E_CAPTURE if the stream is

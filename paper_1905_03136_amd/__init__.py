@@ -7,7 +7,7 @@ Importing the torch API requires the built library.
 
 
 def __getattr__(name):
-    if name in ("tsmttsm", "tsmm", "kernel_name"):
+    if name in ("tsmttsm", "tsmm", "kernel_name", "OrthPlan", "orth_batched"):
         from . import api
         return getattr(api, name)
     if name == "TSMTTSM":

@@ -22,6 +22,12 @@ PROTOTYPES = {
     "tsg_tsmttsm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "tsg_tsmm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
     "tsg_tsmm_op": (_i32, [_i32, _i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
+    "tsg_orth_plan_create": (_i32, [_vp, _i32, _vp, _i64, _vp]),
+    "tsg_orth_plan_launch": (_i32, [_vp, _vp]),
+    "tsg_orth_plan_run": (_i32, [_vp, _vp]),
+    "tsg_orth_plan_check": (_i32, [_vp]),
+    "tsg_orth_plan_set_spin_limit": (_i32, [_vp, ctypes.c_uint32]),
+    "tsg_orth_plan_destroy": (None, [_vp]),
     "tsg_reserve": (_i32, [_i32, _i64, _i32, _i32, _vp]),
     "tsg_workspace_size": (_sz, [_i32, _i64, _i32, _i32]),
     "tsg_init": (_i32, [_i32]),
@@ -35,6 +41,12 @@ PROTOTYPES = {
     "tsg_variant_count": (_i32, []),
     "tsg_variant_name": (ctypes.c_char_p, [_i32]),
 }
+
+
+class tsg_orth_desc(ctypes.Structure):
+    """Instance descriptor of the batched orthogonalisation (layout of the C struct)."""
+    _fields_ = [("K", _i64), ("M", _i32), ("N", _i32), ("V", _vp), ("ldv", _i64),
+                ("W", _vp), ("ldw", _i64), ("C", _vp), ("ldc", _i64)]
 
 
 class TsgError(RuntimeError):
@@ -129,3 +141,32 @@ def tsg_stream_read(x, nbytes, stream):
 
 def tsg_stream_copy(src, dst, nbytes, stream):
     return lib().tsg_stream_copy(src, dst, nbytes, stream)
+
+
+def tsg_orth_plan_create(descs, rows_per_item, stream):
+    """descs: sequence of tsg_orth_desc.  Returns (status, plan handle or None)."""
+    arr = (tsg_orth_desc * len(descs))(*descs)
+    plan = ctypes.c_void_p()
+    st = lib().tsg_orth_plan_create(ctypes.byref(plan), len(descs), arr if len(descs) else None,
+                                    rows_per_item, stream)
+    return st, (plan.value if st == TSG_OK else None)
+
+
+def tsg_orth_plan_launch(plan, stream):
+    return lib().tsg_orth_plan_launch(plan, stream)
+
+
+def tsg_orth_plan_run(plan, stream):
+    return lib().tsg_orth_plan_run(plan, stream)
+
+
+def tsg_orth_plan_check(plan):
+    return lib().tsg_orth_plan_check(plan)
+
+
+def tsg_orth_plan_set_spin_limit(plan, limit):
+    return lib().tsg_orth_plan_set_spin_limit(plan, limit)
+
+
+def tsg_orth_plan_destroy(plan):
+    lib().tsg_orth_plan_destroy(plan)

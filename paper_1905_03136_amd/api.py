@@ -87,3 +87,90 @@ def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False, opC="N"):
 def kernel_name(op, dtype, M, N, conj=False):
     """Name of the kernel variant the library launches for this problem."""
     return _lib.tsg_kernel_name(0 if op == "tsmttsm" else 1, _DT[dtype], int(conj), M, N)
+
+
+class OrthPlan:
+    """Batched block orthogonalisation: for every pair (V_i, W_i),
+    C_i = V_i^T W_i and then W_i <- W_i - V_i C_i, all instances in one
+    persistent kernel launch (replayed from a captured hipGraph).
+
+    V_i (K_i x M_i, M_i <= 64) and W_i (K_i x N_i, N_i <= 16) are row-major
+    float64 tensors on one GPU; W_i is updated in place and C_i (M_i x N_i)
+    is written to ``self.C[i]``.  The tensors must stay alive and must not
+    move while the plan exists.  Launches of one plan must not overlap.
+    """
+
+    def __init__(self, pairs, rows_per_item=0, C=None):
+        if not pairs:
+            raise ValueError("need at least one (V, W) pair")
+        dev = pairs[0][0].device
+        if dev.type != "cuda":
+            raise ValueError("V and W must be on a GPU")
+        self.device = dev
+        self.pairs = list(pairs)
+        self.C = []
+        descs = []
+        for i, (V, W) in enumerate(self.pairs):
+            if V.dtype != torch.float64 or W.dtype != torch.float64:
+                raise TypeError("instance %d: V and W must be float64" % i)
+            if V.device != dev or W.device != dev:
+                raise ValueError("instance %d: all tensors must be on %s" % (i, dev))
+            if V.dim() != 2 or W.dim() != 2 or V.shape[0] != W.shape[0]:
+                raise ValueError("instance %d: V (K x M) and W (K x N) must have the same rows" % i)
+            K, M = V.shape
+            N = W.shape[1]
+            Ci = C[i] if C is not None else torch.empty((M, N), dtype=torch.float64, device=dev)
+            if Ci.shape != (M, N) or Ci.dtype != torch.float64 or Ci.device != dev:
+                raise ValueError("instance %d: C must be an (M, N) float64 tensor on %s" % (i, dev))
+            self.C.append(Ci)
+            descs.append(_lib.tsg_orth_desc(K, M, N, V.data_ptr(), _ld(V, "V"), W.data_ptr(), _ld(W, "W"),
+                                            Ci.data_ptr(), _ld(Ci, "C")))
+        with torch.cuda.device(dev):
+            st, plan = _lib.tsg_orth_plan_create(descs, rows_per_item, _stream(dev))
+        _lib.check(st)
+        self._plan = plan
+
+    def launch(self):
+        """Replay the captured graph on the current stream (asynchronous)."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_plan_launch(self._plan, _stream(self.device)))
+        return self.C
+
+    def run(self):
+        """Launch the persistent kernel directly on the current stream."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_plan_run(self._plan, _stream(self.device)))
+        return self.C
+
+    def check(self):
+        """Wait for the device; raise if a wait inside a launch gave up."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_plan_check(self._plan))
+
+    def set_spin_limit(self, limit):
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_plan_set_spin_limit(self._plan, int(limit)))
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            with torch.cuda.device(self.device):
+                _lib.tsg_orth_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def orth_batched(pairs, rows_per_item=0):
+    """One batched orthogonalisation step over ``pairs`` [(V_i, W_i), ...]:
+    W_i is updated in place, the list of C_i = V_i^T W_i (old W_i) returned."""
+    plan = OrthPlan(pairs, rows_per_item)
+    try:
+        C = plan.launch()
+        plan.check()
+    finally:
+        plan.close()
+    return C

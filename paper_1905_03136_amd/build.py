@@ -67,7 +67,8 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
     gen_dir = GEN + tag
     obj_dir = OBJ + tag
     srcs, variants = generate(widths, variants, gen_dir)
-    srcs = list(srcs) + [os.path.join(CSRC, "tsg_runtime.hip"), os.path.join(CSRC, "tsg_stream.hip")]
+    srcs = list(srcs) + [os.path.join(CSRC, "tsg_runtime.hip"), os.path.join(CSRC, "tsg_stream.hip"),
+                        os.path.join(CSRC, "tsg_batched.hip")]
     OBJD = obj_dir
     os.makedirs(OBJD, exist_ok=True)
     objs = []

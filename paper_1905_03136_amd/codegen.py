@@ -366,3 +366,13 @@ def all_variants(widths=None, tuned_path=None):
             seen.add((M, N))
             uniq.append((M, N))
     return exact_variants(uniq, load_tuned(tuned_path)) + generic_variants()
+
+
+def kernel_symbol(name, tuned=None):
+    """Demangled symbol prefix ("void tsg::...<...>") of the product variant
+    called ``name``, as profilers print it; None if no such variant."""
+    tuned = tuned or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+    for v in all_variants(None, tuned):
+        if variant_name(v) == name:
+            return "void " + _template(v)
+    return None

@@ -1,0 +1,641 @@
+// tsg_batched.hip -- batched block orthogonalisation in one persistent launch.
+//
+// For every instance i:  C_i = V_i^T W_i  (the paper's TSMTTSM, Section 3),
+// then W_i <- W_i - V_i C_i (TSMM, Section 4, with alpha = -1 and beta = 1):
+// the classical Gram-Schmidt projection that uses both products (Section 1.2).
+//
+// One kernel launch with a persistent grid consumes a device work queue:
+//  * phase-1 items: a K-slab of one instance; its partial V^T W goes to the
+//    slab's own slot; the last slab of an instance to finish (per-instance
+//    arrival counter) sums the instance's slots in slab order into C_i and
+//    raises ready[i];
+//  * phase-2 items: a row slab of one instance; waits for ready[i], stages
+//    -C_i on chip and updates its rows of W_i.
+// Every phase-1 item precedes every phase-2 item in the queue and phase-1
+// items never wait, so whatever an update waits for has already been taken by
+// a running block: the waits cannot deadlock, whatever the grid.  They are
+// bounded anyway (a spin limit raises an error word instead of hanging).  The
+// last block to leave returns the queue head, counters and flags to zero, so
+// the launch can be replayed from a captured graph without memset nodes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdint>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/tsgemm.h"
+#include "tsg_device.hpp"
+
+namespace tsg {
+tsg_status report(tsg_status s, const char* msg);  // sets the detail of tsg_last_error()
+}
+
+namespace {
+
+using tsg::dbl4;
+using tsg::kWave;
+
+constexpr int kWPB = 4;  // waves per block
+constexpr int kThreads = kWPB * kWave;
+constexpr int kMaxM = 64, kMaxN = 16;
+constexpr unsigned kDefaultSpin = 1u << 23;   // sleeps of ~0.2 us: about 2 s
+constexpr int64_t kItemBytes = 2 << 20;       // input bytes of one slab (automatic sizing)
+constexpr int64_t kMaxSlabs = 256;            // slabs per instance (bounds the fold)
+
+struct Item {
+    int64_t row0;      // first row of the slab
+    int64_t slot_off;  // phase 1: offset (doubles) of this slab's partial
+    int32_t nrows;
+    int32_t inst;
+    int32_t phase;     // 1: slab of V^T W; 2: update of W rows
+    int32_t pad;
+};
+
+struct DevDesc {
+    int64_t K;
+    const double* V;
+    int64_t ldv;
+    double* W;
+    int64_t ldw;
+    double* C;
+    int64_t ldc;
+    int64_t part0;  // offset (doubles) of the instance's first partial
+    int32_t M, N;
+    int32_t nparts;  // phase-1 slabs of the instance
+    int32_t pad;
+};
+
+struct Ctrl {
+    unsigned head;   // next queue position
+    unsigned done;   // blocks that have left the queue loop
+    unsigned err;    // a wait ran past the spin limit
+    unsigned spin;   // spin limit
+};
+
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// ------------------------------------------------------- slab addressing
+// A slab (rows row0 .. row0 + nrows - 1 of a row-major matrix) is addressed
+// through a raw buffer resource: base and extent live in scalar registers,
+// every lane adds one 32-bit byte offset per row (columns go into the
+// instruction's immediate offset).  The extent ends at the last element of
+// the slab, so an access past it (a row beyond the slab, or a column past the
+// end of the last row) returns zero and a store there is dropped: no address
+// clamps are needed.  The plan keeps every offset below 2^31.
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (CDNA)
+constexpr int kNT = 2;                  // cache policy: streaming (last use)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const double* base, int64_t row0, int32_t nrows,
+                                                           int64_t ld, int cols)
+{
+    const int bytes = nrows > 0 ? (int)(((int64_t)(nrows - 1) * ld + cols) * 8) : 0;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base + row0 * ld), 0, bytes, kRsrcWord3);
+}
+
+template <int AUX>
+__device__ __forceinline__ double ld_buf(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, int off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          off, 0, kNT);
+}
+
+// ------------------------------------------------------- one path per call
+// Every (width class, phase) code path is a function of its own (not
+// inlined), so that each gets its own register allocation: inlined into one
+// loop, the paths' live ranges pile up and spill.  Call arguments arrive in
+// vector registers, so each path re-reads its item and descriptor and makes
+// the fields wave-uniform again (scalar registers, buffer descriptors
+// without waterfall loops).
+__shared__ double g_lds[kMaxM * kMaxN];  // C staging and the cross-wave sums
+
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* p)
+{
+    return reinterpret_cast<T*>(uni(reinterpret_cast<int64_t>(p)));
+}
+
+__device__ __forceinline__ void fetch_item(const Item* items, const DevDesc* descs, int q, Item& it, DevDesc& d)
+{
+    it = uni(items)[uni(q)];
+    it.row0 = uni(it.row0);
+    it.slot_off = uni(it.slot_off);
+    it.nrows = uni(it.nrows);
+    it.inst = uni(it.inst);
+    d = uni(descs)[it.inst];
+    d.K = uni(d.K);
+    d.V = uni(d.V);
+    d.ldv = uni(d.ldv);
+    d.W = uni(d.W);
+    d.ldw = uni(d.ldw);
+    d.C = uni(d.C);
+    d.ldc = uni(d.ldc);
+    d.part0 = uni(d.part0);
+    d.M = uni(d.M);
+    d.N = uni(d.N);
+    d.nparts = uni(d.nparts);
+}
+
+// ---------------------------------------------------------------- phase 1
+// V^T W over one slab, MB m-blocks of 16 (M <= 16 MB) and one n-block
+// (N <= 16).  v_mfma_f64_16x16x4f64 takes lane l's A value as A(l%16, l/16)
+// and its B value as B(l/16, l%16): lane (r = l/16, c = l%16) supplies
+// V(k0 + r, 16 mb + c) and W(k0 + r, c), four rows per product; a step takes
+// U such groups (4U rows).  The waves of the block take every fourth step,
+// loading the next step's rows before the current ones are multiplied.  Rows
+// past the slab read zero.  Lanes whose column is past M or N feed only
+// output rows or columns that are never stored, so they need no guard.
+template <int MB, int U>
+__device__ __attribute__((noinline)) void slab_partial(const Item* items, const DevDesc* descs, int q, double* parts_)
+{
+    Item it;
+    DevDesc d;
+    fetch_item(items, descs, q, it, d);
+    double* __restrict__ parts = uni(parts_);
+    double* lds = g_lds;
+    int lane = threadIdx.x & (kWave - 1);
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform loop bounds
+    // opaque per item: keeps lane-derived offsets of every code path from being
+    // hoisted out of the queue loop (they would all stay live at once)
+    __asm__ volatile("" : "+v"(lane), "+s"(wave));
+    const int lr = lane >> 4, lc = lane & 15;
+    const int M = d.M, N = d.N;
+    const auto rv = slab_rsrc(d.V, it.row0, it.nrows, d.ldv, M);
+    const auto rw = slab_rsrc(d.W, it.row0, it.nrows, d.ldw, N);
+    const int sv = (int)(4 * d.ldv * 8), sw = (int)(4 * d.ldw * 8);  // bytes per four rows
+    const int ov = (int)(lr * d.ldv + lc) * 8, ow = (int)(lr * d.ldw + lc) * 8;
+    dbl4 acc[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+    struct Frag {
+        double a[U][MB];
+        double b[U];
+    };
+    Frag x, y;
+    auto load = [&](int64_t g, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int grp = (int)(U * g + u);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) f.a[u][i] = ld_buf<0>(rv, grp * sv + ov + 128 * i);
+            f.b[u] = ld_buf<0>(rw, grp * sw + ow);
+        }
+    };
+    auto compute = [&](int64_t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < MB; ++i) acc[i] = mfma16(f.a[u][i], f.b[u], acc[i]);
+    };
+    const int64_t nsteps = (it.nrows + 4 * U - 1) / (4 * U);
+    tsg::leapfrog((int64_t)wave, nsteps, (int64_t)kWPB, x, y, load, compute);
+
+    // waves summed in wave order into lds[m * N + n]; lane holds D(l/16 + 4r, l%16)
+    for (int w = 0; w < kWPB; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 16 * i + lr + 4 * r;
+                    if (m < M && lc < N) {
+                        const int e = m * N + lc;
+                        lds[e] = (w == 0) ? acc[i][r] : lds[e] + acc[i][r];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    double* part = parts + it.slot_off;
+    for (int e = threadIdx.x; e < M * N; e += kThreads) part[e] = lds[e];
+}
+
+// Sum of the instance's partials in slab order, eight loads in flight.
+__device__ void fold_instance(const DevDesc& d, const double* __restrict__ parts)
+{
+    const int E = d.M * d.N, P = d.nparts;
+    for (int e = threadIdx.x; e < E; e += kThreads) {
+        const double* p = parts + d.part0 + e;
+        double s = 0.0;
+        int j = 0;
+        for (; j + 8 <= P; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(j + u) * E];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; j < P; ++j) s += p[(int64_t)j * E];
+        const int m = e / d.N, n = e - m * d.N;
+        d.C[(int64_t)m * d.ldc + n] = s;
+    }
+}
+
+// ---------------------------------------------------------------- phase 2
+// W(rows) <- W(rows) + V(rows) (-C), sixteen rows per MFMA chain: lane
+// (r, c) supplies V(row0 + 16 b + c, 4 s + r) as the A value of contraction
+// step s, and the B value -C(4 s + r, c) comes from LDS in fragment order
+// (one conflict-free read per lane and step).  The accumulator starts from
+// the W values the lane owns, W(row0 + 16 b + r + 4 q, c), q = 0..3, loaded
+// with V one step ahead; a step takes U blocks of sixteen rows.  Only the
+// last contraction step can reach past M (4 (MS - 1) < M); its lanes there
+// are zeroed, since the staged C is zero but the loaded value need not be
+// finite.  Rows past the slab read zero and their stores are dropped; lanes
+// whose column is past N neither matter nor store.
+template <int MS, int U>
+__device__ __attribute__((noinline)) void slab_update(const Item* items, const DevDesc* descs, int q)
+{
+    Item it;
+    DevDesc d;
+    fetch_item(items, descs, q, it, d);
+    const double* cf = g_lds;
+    int lane = threadIdx.x & (kWave - 1);
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform loop bounds
+    // opaque per item: keeps lane-derived offsets of every code path from being
+    // hoisted out of the queue loop (they would all stay live at once)
+    __asm__ volatile("" : "+v"(lane), "+s"(wave));
+    const int lr = lane >> 4, lc = lane & 15;
+    const int M = d.M, N = d.N;
+    const auto rv = slab_rsrc(d.V, it.row0, it.nrows, d.ldv, M);
+    const auto rw = slab_rsrc(d.W, it.row0, it.nrows, d.ldw, N);
+    const bool kok = 4 * (MS - 1) + lr < M;
+    const bool nok = lc < N;
+    const int sv = (int)(16 * d.ldv * 8), sw = (int)(16 * d.ldw * 8);  // bytes per sixteen rows
+    const int ov = (int)(lc * d.ldv + lr) * 8;
+    const int ow = (int)(lr * d.ldw + lc) * 8, qw = (int)(4 * d.ldw * 8);
+    struct Frag {
+        double a[U][MS];
+        dbl4 w[U];
+    };
+    Frag x, y;
+    auto load = [&](int64_t g, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int blk = (int)(U * g + u);
+#pragma unroll
+            for (int s = 0; s < MS; ++s) f.a[u][s] = ld_buf<kNT>(rv, blk * sv + ov + 32 * s);
+            f.a[u][MS - 1] = kok ? f.a[u][MS - 1] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f.w[u][q] = ld_buf<kNT>(rw, blk * sw + ow + q * qw);
+        }
+    };
+    auto compute = [&](int64_t g, Frag& f) {
+        __asm__ volatile("" ::: "memory");  // read C from LDS each time (no hoisting into registers)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dbl4 acc = f.w[u];
+#pragma unroll
+            for (int s = 0; s < MS; ++s) acc = mfma16(f.a[u][s], cf[s * kWave + lane], acc);
+            const int blk = (int)(U * g + u);
+            if (nok) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) st_buf(rw, blk * sw + ow + q * qw, acc[q]);
+            }
+        }
+    };
+    const int64_t nsteps = (it.nrows + 16 * U - 1) / (16 * U);
+    tsg::leapfrog((int64_t)wave, nsteps, (int64_t)kWPB, x, y, load, compute);
+}
+
+// Two waves per SIMD: every path fits in 256 registers without spilling.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ items, int total,
+                double* __restrict__ parts, unsigned* __restrict__ cnt, unsigned* __restrict__ ready,
+                Ctrl* __restrict__ ctrl, int count)
+{
+    __shared__ int s_q, s_last;
+    double* lds = g_lds;
+    const int tid = threadIdx.x;
+    while (true) {
+        if (tid == 0)
+            s_q = (int)__hip_atomic_fetch_add(&ctrl->head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int q = __builtin_amdgcn_readfirstlane(s_q);  // uniform: item and descriptor go to SGPRs
+        if (q >= total) break;
+        const Item it = items[q];
+        const DevDesc d = descs[it.inst];
+        if (it.phase == 1) {
+            // rows per step chosen so that a register set holds about 20 values
+            switch ((d.M + 15) / 16) {
+            case 1: slab_partial<1, 8>(items, descs, q, parts); break;
+            case 2: slab_partial<2, 4>(items, descs, q, parts); break;
+            case 3: slab_partial<3, 2>(items, descs, q, parts); break;
+            default: slab_partial<4, 2>(items, descs, q, parts); break;
+            }
+            fence_release();  // this wave's part of the partial, before the arrival is counted
+            __syncthreads();
+            if (tid == 0) {
+                const unsigned old =
+                    __hip_atomic_fetch_add(&cnt[it.inst], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                s_last = old == (unsigned)(d.nparts - 1);
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(s_last)) {
+                fence_acquire();  // every partial of the instance is visible
+                fold_instance(d, parts);
+                fence_release();
+                __syncthreads();
+                if (tid == 0) __hip_atomic_store(&ready[it.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            if (tid == 0) {
+                const unsigned limit = __hip_atomic_load(&ctrl->spin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // bounded wait; the limit is checked first, so a limit of 0 always gives up
+                for (unsigned spins = 0;; ++spins) {
+                    if (spins >= limit) {
+                        __hip_atomic_fetch_or(&ctrl->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    if (__hip_atomic_load(&ready[it.inst], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            __syncthreads();
+            fence_acquire();  // C_i as written by the fold
+            // -C_i in MFMA operand order: lds[s * 64 + l] = -C(4 s + l/16, l%16)
+            const int MS = (d.M + 3) / 4;
+            for (int idx = tid; idx < MS * kWave; idx += kThreads) {
+                const int l = idx & (kWave - 1), s = idx / kWave;
+                const int m = 4 * s + (l >> 4), n = l & 15;
+                lds[idx] = (m < d.M && n < d.N) ? -d.C[(int64_t)m * d.ldc + n] : 0.0;
+            }
+            __syncthreads();
+            switch (MS) {
+            case 1: slab_update<1, 4>(items, descs, q); break;
+            case 2: slab_update<2, 2>(items, descs, q); break;
+            case 3: slab_update<3, 2>(items, descs, q); break;
+            case 4: slab_update<4, 2>(items, descs, q); break;
+            case 5: slab_update<5, 2>(items, descs, q); break;
+            case 6: slab_update<6, 1>(items, descs, q); break;
+            case 7: slab_update<7, 1>(items, descs, q); break;
+            case 8: slab_update<8, 1>(items, descs, q); break;
+            case 9: slab_update<9, 1>(items, descs, q); break;
+            case 10: slab_update<10, 1>(items, descs, q); break;
+            case 11: slab_update<11, 1>(items, descs, q); break;
+            case 12: slab_update<12, 1>(items, descs, q); break;
+            case 13: slab_update<13, 1>(items, descs, q); break;
+            case 14: slab_update<14, 1>(items, descs, q); break;
+            case 15: slab_update<15, 1>(items, descs, q); break;
+            default: slab_update<16, 1>(items, descs, q); break;
+            }
+        }
+        __syncthreads();  // LDS and s_q are reused by the next item
+    }
+    // the last block out resets the queue, counters and flags for the next launch
+    if (tid == 0) {
+        const unsigned old = __hip_atomic_fetch_add(&ctrl->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            for (int i = 0; i < count; ++i) {
+                __hip_atomic_store(&cnt[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ready[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __hip_atomic_store(&ctrl->head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctrl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace
+
+struct tsg_orth_plan_t {
+    int dev = 0;
+    int count = 0;
+    int total = 0;
+    int grid = 0;
+    DevDesc* d_descs = nullptr;
+    Item* d_items = nullptr;
+    double* d_parts = nullptr;
+    unsigned* d_flags = nullptr;  // cnt[count], then ready[count]
+    Ctrl* d_ctrl = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_plan(tsg_orth_plan p)
+{
+    if (!p) return;
+    int cur = 0;
+    const bool switched = hipGetDevice(&cur) == hipSuccess && cur != p->dev && hipSetDevice(p->dev) == hipSuccess;
+    hipDeviceSynchronize();
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->cap) hipStreamDestroy(p->cap);
+    hipFree(p->d_descs);
+    hipFree(p->d_items);
+    hipFree(p->d_parts);
+    hipFree(p->d_flags);
+    hipFree(p->d_ctrl);
+    if (switched) hipSetDevice(cur);
+    delete p;
+}
+
+hipError_t launch(tsg_orth_plan p, hipStream_t s)
+{
+    hipLaunchKernelGGL(orth_persistent, dim3(p->grid), dim3(kThreads), 0, s, p->d_descs, p->d_items, p->total,
+                       p->d_parts, p->d_flags, p->d_flags + p->count, p->d_ctrl, p->count);
+    return hipGetLastError();
+}
+
+int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
+
+tsg_status fail(tsg_status st, const char* fmt, long long a = 0, long long b = 0)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a, b);
+    return tsg::report(st, buf);
+}
+
+}  // namespace
+
+extern "C" {
+
+tsg_status tsg_orth_plan_create(tsg_orth_plan* plan, int32_t count, const tsg_orth_desc* descs,
+                                int64_t rows_per_item, void* stream)
+{
+    (void)stream;
+    if (!plan) return fail(TSG_E_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (!descs || count < 1) return fail(TSG_E_ARG, "need count >= 1 descriptors (count %lld)", count);
+    for (int i = 0; i < count; ++i) {
+        const tsg_orth_desc& s = descs[i];
+        if (s.K < 0 || s.M < 1 || s.N < 1) return fail(TSG_E_ARG, "instance %lld: K < 0, M < 1 or N < 1", i);
+        if (s.M > kMaxM || s.N > kMaxN)
+            return fail(TSG_E_UNSUPPORTED, "instance %lld: M <= 64 and N <= 16 are supported", i);
+        if (s.ldv < s.M || s.ldw < s.N || s.ldc < s.N)
+            return fail(TSG_E_ARG, "instance %lld: leading dimension below the width", i);
+        if (!s.C || (s.K > 0 && (!s.V || !s.W))) return fail(TSG_E_ARG, "instance %lld: NULL pointer", i);
+        if ((reinterpret_cast<uintptr_t>(s.V) | reinterpret_cast<uintptr_t>(s.W) |
+             reinterpret_cast<uintptr_t>(s.C)) % sizeof(double))
+            return fail(TSG_E_ARG, "instance %lld: pointer not aligned to 8 bytes", i);
+    }
+    // instances queued by decreasing input size (ties by index): the largest
+    // folds finish first and the last items of the queue are short
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return descs[a].K * (descs[a].M + descs[a].N) > descs[b].K * (descs[b].M + descs[b].N);
+    });
+    std::vector<DevDesc> dd(count);
+    std::vector<int64_t> rows(count);
+    int64_t part_total = 0;
+    for (int i = 0; i < count; ++i) {
+        const tsg_orth_desc& s = descs[i];
+        // byte offsets inside a slab (plus one step of rows past its end) stay below 2^31
+        const int64_t R_lim = (((int64_t)1 << 31) / (8 * std::max(s.ldv, s.ldw)) - 128) / 16 * 16;
+        int64_t R = rows_per_item;
+        if (R <= 0) {
+            R = std::max<int64_t>(16, round16(kItemBytes / (8 * (int64_t)(s.M + s.N))));
+            R = std::min(std::max(R, round16((s.K + kMaxSlabs - 1) / kMaxSlabs)), R_lim);
+        }
+        if (R < 1 || R > R_lim)
+            return fail(TSG_E_UNSUPPORTED, "instance %lld: slab height must be in [1, %lld] for its leading dimensions",
+                        i, R_lim);
+        rows[i] = R;
+        const int64_t nslab = s.K > 0 ? (s.K + R - 1) / R : 1;  // K = 0: one empty slab sets C = 0
+        if (nslab > ((int64_t)1 << 24)) return fail(TSG_E_UNSUPPORTED, "instance %lld: too many slabs", i);
+        DevDesc d{};
+        d.K = s.K;
+        d.V = s.V;
+        d.ldv = s.ldv;
+        d.W = s.W;
+        d.ldw = s.ldw;
+        d.C = s.C;
+        d.ldc = s.ldc;
+        d.M = s.M;
+        d.N = s.N;
+        d.part0 = part_total;
+        d.nparts = (int32_t)nslab;
+        part_total += nslab * (int64_t)s.M * s.N;
+        dd[i] = d;
+    }
+    std::vector<Item> items;
+    for (int phase = 1; phase <= 2; ++phase)
+        for (int i : order) {
+            const DevDesc& d = dd[i];
+            if (phase == 2 && d.K == 0) continue;
+            for (int64_t j = 0; j < d.nparts; ++j) {
+                Item it{};
+                it.row0 = j * rows[i];
+                it.nrows = (int32_t)std::min(rows[i], d.K - it.row0);
+                it.inst = i;
+                it.phase = phase;
+                it.slot_off = phase == 1 ? d.part0 + j * (int64_t)d.M * d.N : 0;
+                items.push_back(it);
+            }
+        }
+    if (items.size() > ((size_t)1 << 30)) return fail(TSG_E_UNSUPPORTED, "too many work items");
+
+    tsg_orth_plan p = new (std::nothrow) tsg_orth_plan_t();
+    if (!p) return fail(TSG_E_NOMEM, "host allocation failed");
+    p->count = count;
+    p->total = (int)items.size();
+    int cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&p->dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&orth_persistent),
+                                                         kThreads, 0);
+    if (e != hipSuccess || cus < 1) {
+        delete p;
+        return fail(TSG_E_HIP, "no usable HIP device (%lld)", (long long)e);
+    }
+    p->grid = std::max(1, std::min(cus * std::max(occ, 1), p->total));
+    const Ctrl ctrl0{0u, 0u, 0u, kDefaultSpin};
+    if (hipMalloc(&p->d_descs, sizeof(DevDesc) * count) != hipSuccess ||
+        hipMalloc(&p->d_items, sizeof(Item) * items.size()) != hipSuccess ||
+        hipMalloc(&p->d_parts, sizeof(double) * std::max<int64_t>(part_total, 1)) != hipSuccess ||
+        hipMalloc(&p->d_flags, sizeof(unsigned) * 2 * count) != hipSuccess ||
+        hipMalloc(&p->d_ctrl, sizeof(Ctrl)) != hipSuccess) {
+        free_plan(p);
+        return fail(TSG_E_NOMEM, "device allocation of the plan failed");
+    }
+    if (hipMemcpy(p->d_descs, dd.data(), sizeof(DevDesc) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p->d_flags, 0, sizeof(unsigned) * 2 * count) != hipSuccess ||
+        hipMemcpy(p->d_ctrl, &ctrl0, sizeof(Ctrl), hipMemcpyHostToDevice) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        free_plan(p);
+        return fail(TSG_E_HIP, "upload of the plan failed");
+    }
+    // one launch captured on a private stream; replays go to the caller's stream
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        free_plan(p);
+        return fail(TSG_E_HIP, "stream capture could not start");
+    }
+    e = launch(p, p->cap);
+    const hipError_t e2 = hipStreamEndCapture(p->cap, &p->graph);
+    if (e != hipSuccess || e2 != hipSuccess ||
+        hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        free_plan(p);
+        return fail(TSG_E_HIP, "graph capture of the launch failed");
+    }
+    *plan = p;
+    return TSG_OK;
+}
+
+tsg_status tsg_orth_plan_launch(tsg_orth_plan plan, void* stream)
+{
+    if (!plan) return fail(TSG_E_ARG, "plan is NULL");
+    const hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TSG_OK : fail(TSG_E_HIP, "hipGraphLaunch failed (%lld)", (long long)e);
+}
+
+tsg_status tsg_orth_plan_run(tsg_orth_plan plan, void* stream)
+{
+    if (!plan) return fail(TSG_E_ARG, "plan is NULL");
+    const hipError_t e = launch(plan, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TSG_OK : fail(TSG_E_HIP, "kernel launch failed (%lld)", (long long)e);
+}
+
+tsg_status tsg_orth_plan_check(tsg_orth_plan plan)
+{
+    if (!plan) return fail(TSG_E_ARG, "plan is NULL");
+    Ctrl c{};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&c, plan->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TSG_E_HIP, "device synchronisation failed");
+    if (c.err) {
+        const unsigned zero = 0;
+        if (hipMemcpy(&plan->d_ctrl->err, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(TSG_E_HIP, "could not clear the error word");
+        return fail(TSG_E_HIP, "an update waited past the spin limit (%lld sleeps): results invalid", c.spin);
+    }
+    return TSG_OK;
+}
+
+tsg_status tsg_orth_plan_set_spin_limit(tsg_orth_plan plan, uint32_t limit)
+{
+    if (!plan) return fail(TSG_E_ARG, "plan is NULL");
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&plan->d_ctrl->spin, &limit, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TSG_E_HIP, "could not set the spin limit");
+    return TSG_OK;
+}
+
+void tsg_orth_plan_destroy(tsg_orth_plan plan) { free_plan(plan); }
+
+}  // extern "C"

@@ -78,6 +78,19 @@ tsg_status fail(tsg_status s, const char* fmt, ...)
 
 constexpr int kMaxWidth = 64;
 
+}  // namespace
+
+namespace tsg {
+// Error detail for tsg_last_error() from the library's other units.
+tsg_status report(tsg_status s, const char* msg)
+{
+    g_err = msg;
+    return s;
+}
+}  // namespace tsg
+
+namespace {
+
 struct DeviceInfo {
     int cus = 0;
     bool ok = false;

@@ -110,3 +110,52 @@ def test_precision_dtypes_validated(lib):
     # a transposed small matrix is stored N x M: ldc >= M
     assert _lib.tsg_tsmm_op(_lib.TSG_R64, 0, _lib.TSG_OP_T, 10, 6, 4, A, 6, A, 5, A, 4, 1.0, 0.0, None) \
         == _lib.TSG_E_ARG
+
+
+def _desc(K=100, M=8, N=4, V=A, ldv=None, W=A, ldw=None, C=A, ldc=None):
+    return _lib.tsg_orth_desc(K, M, N, V, M if ldv is None else ldv, W, N if ldw is None else ldw,
+                              C, N if ldc is None else ldc)
+
+
+@pytest.mark.parametrize("desc,code", [
+    (dict(K=-1), _lib.TSG_E_ARG),
+    (dict(M=0), _lib.TSG_E_ARG),
+    (dict(N=0), _lib.TSG_E_ARG),
+    (dict(M=65), _lib.TSG_E_UNSUPPORTED),
+    (dict(N=17), _lib.TSG_E_UNSUPPORTED),
+    (dict(ldv=7), _lib.TSG_E_ARG),
+    (dict(ldw=3), _lib.TSG_E_ARG),
+    (dict(ldc=3), _lib.TSG_E_ARG),
+    (dict(V=None), _lib.TSG_E_ARG),
+    (dict(W=None), _lib.TSG_E_ARG),
+    (dict(C=None), _lib.TSG_E_ARG),
+    (dict(K=0, V=None, W=None, C=None), _lib.TSG_E_ARG),   # C is written even for K = 0
+    (dict(V=A + 4), _lib.TSG_E_ARG),
+    (dict(C=A + 2), _lib.TSG_E_ARG),
+    (dict(ldv=1 << 28), _lib.TSG_E_UNSUPPORTED),            # slab offsets would pass 2^31 bytes
+])
+def test_orth_plan_validation(lib, desc, code):
+    good = _desc()
+    st, plan = _lib.tsg_orth_plan_create([good, _desc(**desc)], 0, None)
+    assert st == code and plan is None
+    assert "instance 1" in _lib.tsg_last_error()
+
+
+def test_orth_plan_validation_misc(lib):
+    assert _lib.tsg_orth_plan_create([], 0, None)[0] == _lib.TSG_E_ARG
+    assert lib.tsg_orth_plan_create(None, 1, None, 0, None) == _lib.TSG_E_ARG
+    # a fixed slab height beyond the offset bound of the leading dimension
+    assert _lib.tsg_orth_plan_create([_desc(M=64, ldv=64)], 1 << 30, None)[0] == _lib.TSG_E_UNSUPPORTED
+    for fn in (_lib.tsg_orth_plan_launch, _lib.tsg_orth_plan_run):
+        assert fn(None, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_orth_plan_check(None) == _lib.TSG_E_ARG
+    assert _lib.tsg_orth_plan_set_spin_limit(None, 0) == _lib.TSG_E_ARG
+    _lib.tsg_orth_plan_destroy(None)                      # ignored
+
+
+def test_orth_plan_no_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, plan = _lib.tsg_orth_plan_create([_desc(), _desc(K=0)], 0, None)
+    assert st == _lib.TSG_E_HIP and plan is None
