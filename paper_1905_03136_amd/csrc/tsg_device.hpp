@@ -90,8 +90,12 @@ __device__ __forceinline__ void st_stream(zf* p, zd v)
     __builtin_nontemporal_store(flt2{(float)v.re, (float)v.im}, reinterpret_cast<flt2*>(p));
 }
 
+// Value or zero.  Component-wise selects, never a conditional on the whole
+// struct: that one becomes a branch, the optimiser then sinks the load into
+// it, and a conditionally issued load makes the loop wait for all loads in
+// flight.
 __device__ __forceinline__ double keep(bool ok, double v) { return ok ? v : 0.0; }
-__device__ __forceinline__ zd keep(bool ok, zd v) { return ok ? v : zd{0.0, 0.0}; }
+__device__ __forceinline__ zd keep(bool ok, zd v) { return zd{ok ? v.re : 0.0, ok ? v.im : 0.0}; }
 
 // ------------------------------------------------------- leap-frog driver
 // Grid-stride loop over tiles t = t0, t0 + G, ... < ntiles with two register

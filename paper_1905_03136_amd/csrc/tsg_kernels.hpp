@@ -90,18 +90,22 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
     const int lr = lane >> 4;
     const int lc = lane & 15;
 
+    // Column guards.  Where a compile-time width covers every column a lane can
+    // address, the guard is the constant true: a guard the compiler cannot
+    // prove true makes it turn the guarded load into a branch, and the loop
+    // then waits for every load in flight at each tile.
     int moff[MB], noff[NB];
     bool mok[MB], nok[NB];
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         const int m = (mw * MB + i) * 16 + lc;
-        mok[i] = m < M;
+        mok[i] = (MC && ((MW - 1) * MB + i + 1) * 16 <= MC) || m < M;
         moff[i] = mok[i] ? m : 0;
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int n = j * 16 + lc;
-        nok[j] = n < N;
+        nok[j] = (NC && (j + 1) * 16 <= NC) || n < N;
         noff[j] = nok[j] ? n : 0;
     }
 
@@ -129,14 +133,14 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             const S* ar = A + rc * lda;
             const S* br = B + rc * ldb;
 #pragma unroll
-            for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok && mok[i], ld_stream(ar + moff[i]));
+            for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok & mok[i], ld_stream(ar + moff[i]));
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 // with MW > 1 the waves of a row group read the same B: keep it in cache
                 if constexpr (MW > 1)
-                    f.b[u][j] = keep(ok && nok[j], ld_shared(br + noff[j]));
+                    f.b[u][j] = keep(ok & nok[j], ld_shared(br + noff[j]));
                 else
-                    f.b[u][j] = keep(ok && nok[j], ld_stream(br + noff[j]));
+                    f.b[u][j] = keep(ok & nok[j], ld_stream(br + noff[j]));
             }
         }
     };
@@ -259,7 +263,7 @@ tsmttsm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t l
         for (int u = 0; u < U; ++u) {
             const int64_t r0 = t * RT + (int64_t)(wave * U + u) * RS + q * P;
             const int64_t ra = r0 + (aok ? ha : 0), rb = r0 + (bok ? hb : 0);
-            const bool oka = aok && ra < K, okb = bok && rb < K;
+            const bool oka = aok & (ra < K), okb = bok & (rb < K);
             f.a[u] = keep(oka, ld_stream(A + (oka ? ra : K - 1) * lda + (aok ? ca : 0)));
             f.b[u] = keep(okb, ld_stream(B + (okb ? rb : K - 1) * ldb + (bok ? cb : 0)));
         }
@@ -373,7 +377,7 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
                 for (int i = 0; i < MX; ++i) {
                     const bool in = MC || i < M;
-                    f.a[u][i] = keep(ok && in, ld_stream(ar + (in ? i : 0)));
+                    f.a[u][i] = keep(ok & in, ld_stream(ar + (in ? i : 0)));
                 }
             }
             if constexpr (VB) {
@@ -387,7 +391,7 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 #pragma unroll
                 for (int j = 0; j < NX; ++j) {
                     const bool in = NC || j < N;
-                    f.b[u][j] = keep(ok && in, ld_stream(br + (in ? j : 0)));
+                    f.b[u][j] = keep(ok & in, ld_stream(br + (in ? j : 0)));
                 }
             }
         }
@@ -639,7 +643,8 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
         const int m = VA ? 8 * (s >> 1) + 2 * lr : 4 * s + lr;  // VA: first column of the pair
-        kok[s] = m < M;
+        const int mlast = VA ? 8 * (s >> 1) + 7 : 4 * s + 3;     // largest column any lane reads at s
+        kok[s] = (MC && mlast < MC) || m < M;                     // constant true where MC covers it
         koff[s] = kok[s] ? m : 0;
     }
 
@@ -836,7 +841,7 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int64_t row = r0 + aoff[s];
-                const bool ok = aok[s] && row < K;
+                const bool ok = aok[s] & (row < K);
                 f.a[u][s] = keep(ok, ld_stream(A + (ok ? row : K - 1) * lda + acol[s]));
             }
         }

@@ -18,7 +18,7 @@ have that hash.
 """
 import argparse
 import collections
-import csv
+import sqlite3
 import glob
 import hashlib
 import json
@@ -48,24 +48,35 @@ def short(name):
 
 
 def _one(d, suffix):
-    got = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    got = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
     if not got:
         raise FileNotFoundError("no *%s under %s" % (suffix, d))
     return got[0]
 
 
+def _db(d):
+    """rocprofv3's default output: one SQLite database (rocpd schema) per run."""
+    return sqlite3.connect(_one(d, "_results.db"))
+
+
 def kernel_stats(d):
-    return [dict(name=short(r["Name"]), full=r["Name"], calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
-                 pct=float(r["Percentage"])) for r in csv.DictReader(open(_one(d, "kernel_stats.csv")))]
+    """Per kernel: dispatch count, average duration and share of the total kernel time."""
+    cur = _db(d).cursor()
+    rows = cur.execute("select name, count(*), avg(duration), sum(duration) from kernels group by name").fetchall()
+    total = sum(r[3] for r in rows) or 1
+    out = [dict(name=short(n), full=n, calls=int(c), avg_us=float(a) / 1e3, pct=100.0 * s / total)
+           for n, c, a, s in rows]
+    return sorted(out, key=lambda r: -r["pct"])
 
 
 def counters(d, counter):
     """Per kernel (full name): list of counter values in bytes (the counter
     is in KiB), in dispatch order."""
     out = collections.defaultdict(list)
-    for r in csv.DictReader(open(_one(d, "counter_collection.csv"))):
-        if r["Counter_Name"] == counter:
-            out[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+    cur = _db(d).cursor()
+    for name, value in cur.execute("select kernel_name, value from counters_collection where counter_name = ? "
+                                   "order by dispatch_id", (counter,)):
+        out[name].append(float(value) * 1024.0)
     return out
 
 
