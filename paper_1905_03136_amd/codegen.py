@@ -108,6 +108,11 @@ def _candidates(op, dt, M, N):
                             out.append(c)
                             if w == 4 and two and mw > 1:
                                 out.append(dict(c, OCC=2))
+                            # complex: Gauss's three-product form needs a third
+                            # accumulator set (half the size of the two it replaces)
+                            acc3 = mb * nb * 4 * 3
+                            if cplx and acc3 <= 64 and (w == 4 or acc3 + ops <= 104):
+                                out.append(dict(c, G3=1))
         return out
     if M * cw <= 8 and N * cw <= 8:
         for u in (1, 2, 4):
@@ -128,6 +133,9 @@ def _candidates(op, dt, M, N):
                         if not cplx and M % 8 == 0:
                             out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, VA=1))
                         out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
+                        # complex three-product form: one more accumulator set, C staged three times
+                        if cplx and ops + u * nb * 4 <= (96 if w == 8 else 160):
+                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
     return out
 
 
@@ -244,6 +252,8 @@ def variant_name(v):
         tag += "_v2"
     if c.get("OCC", 1) != 1:
         tag += "_o%d" % c["OCC"]
+    if c.get("G3"):
+        tag += "_g3"
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -260,15 +270,16 @@ def _template(v):
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
                 M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
                 "true" if c["VB"] else "false", c["WPB"])
-        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
-            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), f32)
+        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %s, %s>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), f32,
+            "true" if c.get("G3") else "false")
     if c["kind"] == "valu":
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s>" % (
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s>" % (
         M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false",
-        c.get("OCC", 1), f32)
+        c.get("OCC", 1), f32, "true" if c.get("G3") else "false")
 
 
 def rows_per_tile(v):

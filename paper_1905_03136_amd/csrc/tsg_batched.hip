@@ -162,10 +162,11 @@ __device__ __forceinline__ void fetch_item(const Item* items, const DevDesc* des
 // and its B value as B(l/16, l%16): lane (r = l/16, c = l%16) supplies
 // V(k0 + r, 16 mb + c) and W(k0 + r, c), four rows per product; a step takes
 // U such groups (4U rows).  The waves of the block take every fourth step,
-// loading the next step's rows before the current ones are multiplied.  Rows
-// past the slab read zero.  Lanes whose column is past M or N feed only
-// output rows or columns that are never stored, so they need no guard.
-template <int MB, int U>
+// loading the rows of the next NBUF - 1 steps before the current ones are
+// multiplied.  Rows past the slab read zero.  Lanes whose column is past M or
+// N feed only output rows or columns that are never stored, so they need no
+// guard.
+template <int MB, int U, int NBUF>
 __device__ __attribute__((noinline)) void slab_partial(const Item* items, const DevDesc* descs, int q, double* parts_)
 {
     Item it;
@@ -191,7 +192,7 @@ __device__ __attribute__((noinline)) void slab_partial(const Item* items, const 
         double a[U][MB];
         double b[U];
     };
-    Frag x, y;
+    Frag fr[NBUF];  // register sets in flight (leap frogging)
     auto load = [&](int64_t g, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -208,7 +209,7 @@ __device__ __attribute__((noinline)) void slab_partial(const Item* items, const 
             for (int i = 0; i < MB; ++i) acc[i] = mfma16(f.a[u][i], f.b[u], acc[i]);
     };
     const int64_t nsteps = (it.nrows + 4 * U - 1) / (4 * U);
-    tsg::leapfrog((int64_t)wave, nsteps, (int64_t)kWPB, x, y, load, compute);
+    tsg::pipeline<NBUF>((int64_t)wave, nsteps, (int64_t)kWPB, fr, load, compute);
 
     // waves summed in wave order into lds[m * N + n]; lane holds D(l/16 + 4r, l%16)
     for (int w = 0; w < kWPB; ++w) {
@@ -257,12 +258,12 @@ __device__ void fold_instance(const DevDesc& d, const double* __restrict__ parts
 // step s, and the B value -C(4 s + r, c) comes from LDS in fragment order
 // (one conflict-free read per lane and step).  The accumulator starts from
 // the W values the lane owns, W(row0 + 16 b + r + 4 q, c), q = 0..3, loaded
-// with V one step ahead; a step takes U blocks of sixteen rows.  Only the
+// with V NBUF - 1 steps ahead; a step takes U blocks of sixteen rows.  Only the
 // last contraction step can reach past M (4 (MS - 1) < M); its lanes there
 // are zeroed, since the staged C is zero but the loaded value need not be
 // finite.  Rows past the slab read zero and their stores are dropped; lanes
 // whose column is past N neither matter nor store.
-template <int MS, int U>
+template <int MS, int U, int NBUF>
 __device__ __attribute__((noinline)) void slab_update(const Item* items, const DevDesc* descs, int q)
 {
     Item it;
@@ -287,7 +288,7 @@ __device__ __attribute__((noinline)) void slab_update(const Item* items, const D
         double a[U][MS];
         dbl4 w[U];
     };
-    Frag x, y;
+    Frag fr[NBUF];  // register sets in flight (leap frogging)
     auto load = [&](int64_t g, Frag& f) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -314,7 +315,7 @@ __device__ __attribute__((noinline)) void slab_update(const Item* items, const D
         }
     };
     const int64_t nsteps = (it.nrows + 16 * U - 1) / (16 * U);
-    tsg::leapfrog((int64_t)wave, nsteps, (int64_t)kWPB, x, y, load, compute);
+    tsg::pipeline<NBUF>((int64_t)wave, nsteps, (int64_t)kWPB, fr, load, compute);
 }
 
 // Two waves per SIMD: every path fits in 256 registers without spilling.
@@ -337,10 +338,10 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
         if (it.phase == 1) {
             // rows per step chosen so that a register set holds about 20 values
             switch ((d.M + 15) / 16) {
-            case 1: slab_partial<1, 8>(items, descs, q, parts); break;
-            case 2: slab_partial<2, 4>(items, descs, q, parts); break;
-            case 3: slab_partial<3, 2>(items, descs, q, parts); break;
-            default: slab_partial<4, 2>(items, descs, q, parts); break;
+            case 1: slab_partial<1, 8, 2>(items, descs, q, parts); break;
+            case 2: slab_partial<2, 4, 2>(items, descs, q, parts); break;
+            case 3: slab_partial<3, 2, 2>(items, descs, q, parts); break;
+            default: slab_partial<4, 2, 2>(items, descs, q, parts); break;
             }
             fence_release();  // this wave's part of the partial, before the arrival is counted
             __syncthreads();
@@ -381,22 +382,22 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
             }
             __syncthreads();
             switch (MS) {
-            case 1: slab_update<1, 4>(items, descs, q); break;
-            case 2: slab_update<2, 2>(items, descs, q); break;
-            case 3: slab_update<3, 2>(items, descs, q); break;
-            case 4: slab_update<4, 2>(items, descs, q); break;
-            case 5: slab_update<5, 2>(items, descs, q); break;
-            case 6: slab_update<6, 1>(items, descs, q); break;
-            case 7: slab_update<7, 1>(items, descs, q); break;
-            case 8: slab_update<8, 1>(items, descs, q); break;
-            case 9: slab_update<9, 1>(items, descs, q); break;
-            case 10: slab_update<10, 1>(items, descs, q); break;
-            case 11: slab_update<11, 1>(items, descs, q); break;
-            case 12: slab_update<12, 1>(items, descs, q); break;
-            case 13: slab_update<13, 1>(items, descs, q); break;
-            case 14: slab_update<14, 1>(items, descs, q); break;
-            case 15: slab_update<15, 1>(items, descs, q); break;
-            default: slab_update<16, 1>(items, descs, q); break;
+            case 1: slab_update<1, 4, 2>(items, descs, q); break;
+            case 2: slab_update<2, 2, 2>(items, descs, q); break;
+            case 3: slab_update<3, 2, 2>(items, descs, q); break;
+            case 4: slab_update<4, 2, 2>(items, descs, q); break;
+            case 5: slab_update<5, 2, 2>(items, descs, q); break;
+            case 6: slab_update<6, 1, 2>(items, descs, q); break;
+            case 7: slab_update<7, 1, 2>(items, descs, q); break;
+            case 8: slab_update<8, 1, 2>(items, descs, q); break;
+            case 9: slab_update<9, 1, 2>(items, descs, q); break;
+            case 10: slab_update<10, 1, 2>(items, descs, q); break;
+            case 11: slab_update<11, 1, 2>(items, descs, q); break;
+            case 12: slab_update<12, 1, 2>(items, descs, q); break;
+            case 13: slab_update<13, 1, 2>(items, descs, q); break;
+            case 14: slab_update<14, 1, 2>(items, descs, q); break;
+            case 15: slab_update<15, 1, 2>(items, descs, q); break;
+            default: slab_update<16, 1, 2>(items, descs, q); break;
             }
         }
         __syncthreads();  // LDS and s_q are reused by the next item

@@ -55,6 +55,12 @@ __device__ __forceinline__ int64_t small_index(int m, int n, int64_t ldc, int op
 // Complex data use four real products per complex block,
 //   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br,
 // with each lane holding the (re, im) pair of one element (one 16-byte load).
+// With G3 they use three (Gauss's form of the complex product):
+//   P1 += Ar Br,  P2 += Ai Bi,  P3 += (Ar + Ai)(Br + Bi),
+//   Cr = P1 - P2,  Ci = P3 - P1 - P2,
+// a quarter fewer matrix-core products for two vector additions per loaded
+// element.  The sums are the same up to rounding; the error bound of Ci
+// grows by a small constant factor (|Ar + Ai||Br + Bi| <= 2 |A||B|).
 //
 // Waves of a block are arranged as RG row groups x MW m-slices: the MW waves
 // of a row group share the same rows and split the m-blocks of C between
@@ -64,7 +70,7 @@ __device__ __forceinline__ int64_t small_index(int m, int n, int64_t ldc, int op
 // in-bounds probe): lane l, element r holds D(l / 16 + 4 r, l % 16).
 // ============================================================================
 template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1,
-          bool F32 = false>
+          bool F32 = false, bool G3 = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
@@ -109,14 +115,17 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
         noff[j] = nok[j] ? n : 0;
     }
 
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
     dbl4 acc[MB][NB];
     dbl4 acci[CPLX ? MB : 1][CPLX ? NB : 1];
+    dbl4 accs[G3 ? MB : 1][G3 ? NB : 1];  // G3: P1 in acc, P2 in acci, P3 in accs
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
             if constexpr (CPLX) acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (G3) accs[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
 
     struct Frag {
@@ -152,6 +161,29 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
                     for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i], f.b[u][j], acc[i][j]);
+            } else if constexpr (G3) {
+                // three passes over all blocks, so the updates of one
+                // accumulator are MB NB instructions apart
+                double ai[MB], sa[MB], sb[NB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    ai[i] = conj ? -f.a[u][i].im : f.a[u][i].im;
+                    sa[i] = f.a[u][i].re + ai[i];
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) sb[j] = f.b[u][j].re + f.b[u][j].im;
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i].re, f.b[u][j].re, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acci[i][j] = mfma16(ai[i], f.b[u][j].im, acci[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) accs[i][j] = mfma16(sa[i], sb[j], accs[i][j]);
             } else {
                 // All products with Re(a) first, then those with Im(a): the two
                 // updates of one accumulator are 2 MB NB instructions apart
@@ -180,6 +212,17 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
     };
     const int64_t ntiles = (K + RT - 1) / RT;
     pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
+    if constexpr (G3) {
+        // Cr = P1 - P2, Ci = P3 - P1 - P2
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const dbl4 p1 = acc[i][j], p2 = acci[i][j];
+                acc[i][j] = p1 - p2;
+                acci[i][j] = accs[i][j] - p1 - p2;
+            }
+    }
 
     // Fold the row groups into the block partial, one group after the other.
     const int E = M * N * CW;
@@ -592,7 +635,7 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
 template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1,
-          bool F32 = false>
+          bool F32 = false, bool G3 = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
@@ -602,13 +645,17 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     // lane of k-slot q, which serve the steps s = 2t (even column) and 2t + 1
     // (odd column); the contraction order over m is permuted accordingly,
     // m(s, q) = 8 (s / 2) + 2 q + s % 2, and C is staged in the same order.
+    // G3 (complex): Gauss's three-product form, P1 = Ar Cr, P2 = Ai Ci,
+    // P3 = (Ar + Ai)(Cr + Ci), Br = P1 - P2, Bi = P3 - P1 - P2; Cr + Ci is
+    // staged beside Cr and Ci.
     static_assert(!VA || (!CPLX && !F32 && MS % 2 == 0), "paired A loads: binary64 real data, M a multiple of 8");
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
     using T = elem_t<CPLX>;
     using S = typename storage<CPLX, F32>::type;  // storage type of A and B
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RT = 16 * U * WPB;
     constexpr int NFRAG = MS * NB * kWave;
-    __shared__ double cf[NFRAG * CW];
+    __shared__ double cf[NFRAG * (G3 ? 3 : CW)];
 
     const S* __restrict__ A = static_cast<const S*>(Av);
     S* __restrict__ B = static_cast<S*>(Bv);
@@ -630,8 +677,11 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         const bool ok = m < M && n < N;
         if constexpr (CPLX) {
             const int64_t ci = small_index(m, n, ldc, opc);
-            cf[idx] = ok ? Cm[2 * ci] : 0.0;
-            cf[NFRAG + idx] = ok ? (opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0;
+            const double re = ok ? Cm[2 * ci] : 0.0;
+            const double im = ok ? (opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0;
+            cf[idx] = re;
+            cf[NFRAG + idx] = im;
+            if constexpr (G3) cf[2 * NFRAG + idx] = re + im;
         } else {
             cf[idx] = ok ? Cm[small_index(m, n, ldc, opc)] : 0.0;
         }
@@ -677,12 +727,14 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         __asm__ volatile("" ::: "memory");
         dbl4 acc[U][NB];
         dbl4 acci[CPLX ? U : 1][CPLX ? NB : 1];
+        dbl4 accs[G3 ? U : 1][G3 ? NB : 1];  // G3: P1 in acc, P2 in acci, P3 in accs
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 acc[u][j] = dbl4{0.0, 0.0, 0.0, 0.0};
                 if constexpr (CPLX) acci[u][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+                if constexpr (G3) accs[u][j] = dbl4{0.0, 0.0, 0.0, 0.0};
             }
 #pragma unroll
         for (int s = 0; s < MS; ++s) {
@@ -692,6 +744,31 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                     const double cr = cf[(s * NB + j) * kWave + lane];
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s], cr, acc[u][j]);
+                }
+            } else if constexpr (G3) {
+                double ai[U], sa[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    ai[u] = conj ? -f.a[u][s].im : f.a[u][s].im;
+                    sa[u] = f.a[u][s].re + ai[u];
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const double cr = cf[(s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s].re, cr, acc[u][j]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const double ci = cf[NFRAG + (s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acci[u][j] = mfma16(ai[u], ci, acci[u][j]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const double cs = cf[2 * NFRAG + (s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) accs[u][j] = mfma16(sa[u], cs, accs[u][j]);
                 }
             } else {
                 // products with Re(a) for every block first, then those with
@@ -718,6 +795,16 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                         acci[u][j] = mfma16(ai, cr[j], acci[u][j]);
                     }
             }
+        }
+        if constexpr (G3) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const dbl4 p1 = acc[u][j], p2 = acci[u][j];
+                    acc[u][j] = p1 - p2;
+                    acci[u][j] = accs[u][j] - p1 - p2;
+                }
         }
         const bool full = (t + 1) * RT <= K;
 #pragma unroll
