@@ -253,22 +253,26 @@ def main():
     torch.cuda.set_device(dev)
     print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
     K = K_SWEEP
-    bufA = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_A, c, dev) for c in (False, True)}
-    bufB = {c: inputs.device_uniform(K, 64, 0, inputs.STREAM_B, c, dev) for c in (False, True)}
+    # Every width has its own exact-size A (K x M) and B (K x N), as a caller's
+    # matrices would be (134 GB in all); TSMTTSM reads them, TSMM reads A and
+    # writes B.  (Prefix views of one wide buffer instead made some TSMM widths
+    # up to 25% slower for reasons outside the kernels.)
+    bufs = {}
+    for cplx in (False, True):
+        for i, (M, N) in enumerate(WIDTHS):
+            bufs[cplx, M, N] = (inputs.device_uniform(K, M, i, inputs.STREAM_A, cplx, dev),
+                                inputs.device_uniform(K, N, i, inputs.STREAM_B, cplx, dev))
     smallC = {c: inputs.device_uniform(64, 64, 0, inputs.STREAM_C, c, dev) for c in (False, True)}
     # Call order: per dtype all TSMTTSM widths, then all TSMM widths, each in
     # FLUSH_ORDER (a wide call between any two narrow ones), so that no call
     # finds the data of the call before it in the 256 MB Infinity Cache.
     calls = []
     for cplx in (False, True):
-        flatA = bufA[cplx].reshape(-1)
-        flatB = bufB[cplx].reshape(-1)
         for op in ("tsmttsm", "tsmm"):
             for (M, N) in FLUSH_ORDER:
-                Av = flatA[:K * M].view(K, M)
-                Bv = flatB[:K * N].view(K, N)
+                Av, Bv = bufs[cplx, M, N]
                 if op == "tsmttsm":
-                    Cout = torch.empty((M, N), dtype=bufA[cplx].dtype, device=dev)
+                    Cout = torch.empty((M, N), dtype=Av.dtype, device=dev)
                     fn = (lambda Av=Av, Bv=Bv, Cout=Cout: api.tsmttsm(Av, Bv, out=Cout))
                 else:
                     Cin = smallC[cplx][:M, :N].contiguous()
@@ -290,7 +294,7 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
-    bs = measure_bs(torch, bufA[True], bufB[True])
+    bs = measure_bs(torch, *bufs[True, 64, 64])   # 16 GiB each
     print("[bench] warmup done; b_s read %.0f GB/s, copy %.0f GB/s; timing %d steps"
           % (bs["read"] / 1e9, bs["copy"] / 1e9, a.steps), file=sys.stderr, flush=True)
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
@@ -340,8 +344,7 @@ def main():
 
     if not a.no_check:
         # spot check of the timed buffers: one TSMTTSM entry against a direct FP64 dot product
-        Av = bufA[False].reshape(-1)[:K * 8].view(K, 8)
-        Bv = bufB[False].reshape(-1)[:K * 8].view(K, 8)
+        Av, Bv = bufs[False, 8, 8]
         C = api.tsmttsm(Av, Bv)
         ref = torch.dot(Av[:, 3].contiguous(), Bv[:, 5].contiguous())
         assert abs(float(C[3, 5] - ref)) <= 1e-10 * float(torch.dot(Av[:, 3].abs(), Bv[:, 5].abs()))
@@ -362,7 +365,7 @@ def main():
         "widths": per,
     }
     if not a.no_forms:
-        del bufA, bufB, calls
+        del bufs, calls
         torch.cuda.empty_cache()
         print("[bench] precision form (binary32 storage) at K=2^25", file=sys.stderr, flush=True)
         out["precision_form"] = precision_form(torch, api, inputs, dev)
