@@ -86,23 +86,28 @@ def _candidates(op, dt, M, N):
                                     VB=int(not cplx and N % 2 == 0), WPB=WPB))
         if M > 8 or N > 8:
             mbt, nb = _ceil(M, 16), _ceil(N, 16)
-            for mw in (1, 2, 4):
+            for mw in (1, 2, 3, 4):
                 if (mbt % mw and mw > 1) or mw > mbt:
                     continue
                 mb = _ceil(mbt, mw)
                 acc = mb * nb * 4 * cw
-                for w in (4, 8):
-                    if w % mw or acc > 64:
+                # three m-slices (widths 33..48) need blocks of a multiple of three waves
+                for w in ((6, 12) if mw == 3 else (4, 8)):
+                    # 256-thread blocks may use the whole register file of one
+                    # wave per SIMD: room for the 3 x 3 complex block grid
+                    # (widths 33..48), which no wave split divides
+                    if w % mw or acc > (72 if w == 4 else 64):
                         continue
                     for u in (1, 2, 4):
                         for nbuf in (2, 3, 4):
                             ops = nbuf * u * (mb + nb) * cw
                             if ops > 72 or (nbuf > 2 and u > 2):
                                 continue
-                            # two waves per SIMD (OCC = 2, implied by 512-thread
-                            # blocks) leave each lane 256 registers in all
+                            # two waves per SIMD (OCC = 2, implied by 384- and
+                            # 512-thread blocks) leave each lane 256 registers in
+                            # all, three (768 threads) about 170
                             two = acc + ops <= 104
-                            if w == 8 and not two:
+                            if (w > 4 and not two) or (w == 12 and acc + ops > 72):
                                 continue
                             c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf)
                             out.append(c)

@@ -807,6 +807,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 }
         }
         const bool full = (t + 1) * RT <= K;
+        constexpr bool kStream = stream_rows(NC * (int)sizeof(S));  // whole lines per row (see st_plain)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t rbase = t * RT + (int64_t)(wave * U + u) * 16 + lr;
@@ -822,14 +823,14 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                             if constexpr (!CPLX) {
                                 double v = alpha * acc[u][j][r];
                                 if (read_b) v = __builtin_fma(beta, ld_plain(p), v);
-                                st_stream(p, v);
+                                st_out<kStream>(p, v);
                             } else {
                                 zd v = zd{alpha * acc[u][j][r], alpha * acci[u][j][r]};
                                 if (read_b) {
                                     const zd o = ld_plain(p);
                                     v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
                                 }
-                                st_stream(p, v);
+                                st_out<kStream>(p, v);
                             }
                         }
                     }
@@ -961,6 +962,7 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             }
         }
         const bool full = (t + 1) * (int64_t)RT <= K;
+        constexpr bool kStream = stream_rows(NC * (int)sizeof(ST));  // whole lines per row (see st_plain)
         if (jok) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -973,14 +975,14 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                         if constexpr (!CPLX) {
                             double v = alpha * acc[u][r];
                             if (read_b) v = __builtin_fma(beta, ld_plain(p), v);
-                            st_stream(p, v);
+                            st_out<kStream>(p, v);
                         } else {
                             zd v = zd{alpha * acc[u][r], alpha * acci[u][r]};
                             if (read_b) {
                                 const zd o = ld_plain(p);
                                 v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
                             }
-                            st_stream(p, v);
+                            st_out<kStream>(p, v);
                         }
                     }
                 }

@@ -95,6 +95,25 @@ def test_integer_inputs_bit_exact(M, N, cplx):
         assert np.array_equal(host(api.tsmm(dA, dX, conjA=True)), oracle.tsmm(A, X, conjA=True))
 
 
+@pytest.mark.parametrize("w", range(1, 65))
+@pytest.mark.parametrize("cplx", [False, True])
+def test_every_square_width(w, cplx):
+    """Each square width runs its own (tuned or default) variant: both products
+    against the compensated oracle, integer inputs bit for bit."""
+    K = 20011                                       # several tiles and a ragged tail
+    A = inputs.host_uniform(K, w, 23, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, w, 23, inputs.STREAM_B, cplx)
+    X = inputs.host_uniform(w, w, 23, inputs.STREAM_C, cplx)
+    dA, dB, dX = dev(A), dev(B), dev(X)
+    check_close(host(api.tsmttsm(dA, dB)), oracle.tsmttsm(A, B, compensated=True), abs_bound_tsmttsm(A, B, "T"))
+    check_close(host(api.tsmm(dA, dX)), oracle.tsmm(A, X, compensated=True), np.abs(A) @ np.abs(X))
+    Ai = inputs.host_integers(K, w, 24, inputs.STREAM_A, cplx)
+    Bi = inputs.host_integers(K, w, 24, inputs.STREAM_B, cplx)
+    Xi = inputs.host_integers(w, w, 24, inputs.STREAM_C, cplx)
+    assert np.array_equal(host(api.tsmttsm(dev(Ai), dev(Bi))), oracle.tsmttsm(Ai, Bi))
+    assert np.array_equal(host(api.tsmm(dev(Ai), dev(Xi))), oracle.tsmm(Ai, Xi))
+
+
 @pytest.mark.parametrize("K", [0, 1, 3, 4, 63, 64, 65, 255, 257, 1023, 4097])
 @pytest.mark.parametrize("M,N", [(1, 1), (4, 4), (8, 8), (32, 32), (64, 64), (3, 17)])
 def test_small_and_ragged_K(K, M, N):

@@ -16,7 +16,9 @@ from paper_1905_03136_amd.tune import TUNE_LIB
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-WIDTHS = codegen.GRADED + [(3, 5), (13, 7)]
+# the sweep widths, two odd pairs, and every square width (skipped where the
+# tuning library was built without its candidates)
+WIDTHS = codegen.GRADED + [(3, 5), (13, 7)] + [w for w in codegen.SQUARE_ALL if w not in codegen.GRADED]
 
 
 @pytest.fixture(scope="module")
