@@ -232,7 +232,8 @@ const char *tsg_status_string(tsg_status s);
 /* Thread-local description of the calling thread's last error ("" if none). */
 const char *tsg_last_error(void);
 
-/* Name of the kernel variant the library would launch for this problem
+/* Name of the kernel variant the library would launch for this problem with
+ * contiguous rows (lda = M, ldb = N) and 16-byte aligned operands
  * (diagnostics and profiling).  op_kind: 0 = TSMTTSM, 1 = TSMM.  Returns a
  * static string, "" if the shape is invalid. */
 const char *tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t M, int32_t N);

@@ -141,6 +141,19 @@ def _candidates(op, dt, M, N):
                         # complex three-product form: one more accumulator set, C staged three times
                         if cplx and ops + u * nb * 4 <= (96 if w == 8 else 160):
                             out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
+        # slab reads of A (rows contiguous): the wave's 16 U rows as one run of
+        # loads of up to 16 bytes per lane, redistributed through LDS
+        if not cplx:
+            es = 4 if is_f32(dt) else 8                       # bytes per stored element
+            fl = max(f for f in (1, 2, 4) if M % f == 0 and f * es <= 16)
+            for u in (1, 2, 4):
+                for w in (4, 8):
+                    for nbuf in (2, 3):
+                        nl = _ceil(16 * u * M, 64 * fl) * fl * es // 8   # registers (doubles) per lane and tile
+                        ops = nbuf * nl + u * ms + u * nb * 4
+                        lds = w * 16 * u * M * es + ms * nb * 64 * 8
+                        if ops <= (96 if w == 8 else 160) and lds <= 64 * 1024 and (nbuf == 2 or u <= 2):
+                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, FL=fl))
     return out
 
 
@@ -217,14 +230,31 @@ def tuning_variants(widths):
 
 
 def load_tuned(path):
+    """{(op, dt, M, N): cfg} of the tuning table; an entry whose fastest
+    configuration has access requirements (paired or slab reads of A) also
+    names the fastest one without them, under the key (op, dt, M, N, "plain")."""
+    out = {}
     if path and os.path.exists(path):
         with open(path) as f:
             tab = json.load(f)
-        return {(e["op"], e["dt"], int(e["M"]), int(e["N"])): e["cfg"] for e in tab.get("entries", [])}
-    return {}
+        for e in tab.get("entries", []):
+            key = (e["op"], e["dt"], int(e["M"]), int(e["N"]))
+            out[key] = e["cfg"]
+            if e.get("plain_cfg"):
+                out[key + ("plain",)] = e["plain_cfg"]
+    return out
+
+
+def needs_layout(cfg):
+    """True if a configuration reads A in a way only some layouts allow."""
+    return bool(cfg.get("VA") or cfg.get("FL"))
 
 
 def exact_variants(widths, tuned=None):
+    """One variant per (op, dtype, width); where the chosen one needs a layout
+    of A (paired or slab reads), a second one without that need follows it,
+    so calls with another leading dimension or alignment keep an exact-width
+    kernel (the runtime takes the first record whose requirements hold)."""
     tuned = tuned or {}
     out = []
     for op in OPS:
@@ -234,6 +264,10 @@ def exact_variants(widths, tuned=None):
                     continue
                 cfg = tuned.get((op, dt, M, N)) or default_config(op, dt, M, N)
                 out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=cfg))
+                if needs_layout(cfg):
+                    plain = tuned.get((op, dt, M, N, "plain")) or default_config(op, dt, M, N)
+                    if not needs_layout(plain):
+                        out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=plain))
     return out
 
 
@@ -259,6 +293,8 @@ def variant_name(v):
         tag += "_o%d" % c["OCC"]
     if c.get("G3"):
         tag += "_g3"
+    if c.get("FL"):
+        tag += "_f%d" % c["FL"]
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -282,9 +318,9 @@ def _template(v):
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s>" % (
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s, %d>" % (
         M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false",
-        c.get("OCC", 1), f32, "true" if c.get("G3") else "false")
+        c.get("OCC", 1), f32, "true" if c.get("G3") else "false", c.get("FL", 0))
 
 
 def rows_per_tile(v):
@@ -313,13 +349,14 @@ def _launcher(v, fn):
 
 def _record(v, fn):
     c = v["cfg"]
-    pair_a = int(c["kind"] in ("valu", "mfma") and bool(c.get("VA")))
+    pair_a = int(c["kind"] in ("valu", "mfma") and (bool(c.get("VA")) or c.get("FL", 0) >= 2))
     pair_x = int(c["kind"] == "valu" and bool(c.get("VB")))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)
-    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
+    flat_a = int(bool(c.get("FL")))
+    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
             % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
-               64 * c["WPB"], rows_per_tile(v), pack, variant_name(v), fn.replace("launch_", "kernel_"), fn))
+               64 * c["WPB"], rows_per_tile(v), pack, flat_a, variant_name(v), fn.replace("launch_", "kernel_"), fn))
 
 
 def emit(outdir, variants, per_file=6):

@@ -634,8 +634,32 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // rows l/16 + 4r (r < 4) of column l%16 of each 16 x 16 output block: sixteen
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
+// Registers of one tile of A: per-row fragments, or (slab reads) the lane's
+// share of the wave's contiguous slab, FL storage elements per load.
+template <class T, int U, int MS>
+struct row_regs {
+    T a[U][MS];
+};
+template <class SV, int NL>
+struct slab_regs {
+    SV v[NL];
+};
+typedef float flt4 __attribute__((ext_vector_type(4)));
+template <class S, int FL>
+struct slab_vec;
+template <>
+struct slab_vec<double, 1> { typedef double type; };
+template <>
+struct slab_vec<double, 2> { typedef dbl2 type; };
+template <>
+struct slab_vec<float, 1> { typedef float type; };
+template <>
+struct slab_vec<float, 2> { typedef flt2 type; };
+template <>
+struct slab_vec<float, 4> { typedef flt4 type; };
+
 template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1,
-          bool F32 = false, bool G3 = false>
+          bool F32 = false, bool G3 = false, int FL = 0>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
@@ -648,14 +672,29 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     // G3 (complex): Gauss's three-product form, P1 = Ar Cr, P2 = Ai Ci,
     // P3 = (Ar + Ai)(Cr + Ci), Br = P1 - P2, Bi = P3 - P1 - P2; Cr + Ci is
     // staged beside Cr and Ci.
+    // FL (real data with contiguous rows, lda == M): the 16 U rows of a wave
+    // are one run of 16 U M elements, read as consecutive loads of FL
+    // elements per lane (binary64: 8 or 16 bytes; binary32: 4, 8 or 16
+    // bytes; M a multiple of FL, A 16-byte aligned), so every load
+    // instruction of the wave covers one contiguous piece whatever M is.
+    // The wave writes the run to its own LDS region and reads the
+    // matrix-core operands A(row, 4s + l/16) back from there; only the wave
+    // itself touches the region, and one wave's LDS accesses complete in
+    // order, so no barrier is needed.
     static_assert(!VA || (!CPLX && !F32 && MS % 2 == 0), "paired A loads: binary64 real data, M a multiple of 8");
     static_assert(CPLX || !G3, "the three-product form is for complex data");
+    static_assert(FL == 0 || (!CPLX && !VA && MC > 0 && MC % FL == 0), "slab reads: real data, M a multiple of FL");
     using T = elem_t<CPLX>;
     using S = typename storage<CPLX, F32>::type;  // storage type of A and B
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RT = 16 * U * WPB;
     constexpr int NFRAG = MS * NB * kWave;
+    constexpr int SLAB = FL ? 16 * U * MC : 0;               // elements of A per wave and tile
+    constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
+    using SR = typename std::conditional<CPLX, double, S>::type;  // real storage type (slab reads)
+    using SV = typename slab_vec<SR, FL ? FL : 1>::type;          // one slab load of a lane
     __shared__ double cf[NFRAG * (G3 ? 3 : CW)];
+    __shared__ __attribute__((aligned(16))) SR slab[FL ? WPB * SLAB : 1];
 
     const S* __restrict__ A = static_cast<const S*>(Av);
     S* __restrict__ B = static_cast<S*>(Bv);
@@ -698,11 +737,25 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         koff[s] = kok[s] ? m : 0;
     }
 
-    struct Frag {
-        T a[U][MS];
-    };
+    using Frag = typename std::conditional<FL != 0, slab_regs<SV, NL>, row_regs<T, U, MS>>::type;
     Frag fr[NBUF];
+    const int64_t KM = K * (int64_t)M;  // slab reads: elements of A
+    SR* const mine = slab + (FL ? wave * SLAB : 0);
     auto load = [&](int64_t t, Frag& f) {
+        if constexpr (FL) {
+            // the wave's run starts at row t RT + 16 U wave; positions past
+            // the end of A are clamped to its last FL elements (K M is a
+            // multiple of FL), their rows are never stored
+            const int64_t base = (t * RT + (int64_t)wave * U * 16) * MC;
+            const SR* As = reinterpret_cast<const SR*>(A);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int64_t e = base + (int64_t)(i * kWave + lane) * FL;
+                const int64_t ec = e <= KM - FL ? e : KM - FL;
+                f.v[i] = __builtin_nontemporal_load(reinterpret_cast<const SV*>(As + ec));
+            }
+            return;
+        } else {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lc;
@@ -720,11 +773,30 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 for (int s = 0; s < MS; ++s) f.a[u][s] = keep(kok[s], ld_stream(ar + koff[s]));
             }
         }
+        }
     };
     auto compute = [&](int64_t t, Frag& f) {
         // Compiler-only barrier: keeps the loop-invariant C operands in LDS
         // instead of letting them be hoisted into (too many) registers.
         __asm__ volatile("" ::: "memory");
+        T av[U][MS];  // matrix-core A operands of the tile
+        if constexpr (FL) {
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int o = (i * kWave + lane) * FL;
+                if (i + 1 < NL || o < SLAB) *reinterpret_cast<SV*>(mine + o) = f.v[i];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int s = 0; s < MS; ++s)
+                    av[u][s] = keep(kok[s], (double)mine[(u * 16 + lc) * MC + koff[s]]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int s = 0; s < MS; ++s) av[u][s] = f.a[u][s];
+        }
         dbl4 acc[U][NB];
         dbl4 acci[CPLX ? U : 1][CPLX ? NB : 1];
         dbl4 accs[G3 ? U : 1][G3 ? NB : 1];  // G3: P1 in acc, P2 in acci, P3 in accs
@@ -743,20 +815,20 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 for (int j = 0; j < NB; ++j) {
                     const double cr = cf[(s * NB + j) * kWave + lane];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s], cr, acc[u][j]);
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(av[u][s], cr, acc[u][j]);
                 }
             } else if constexpr (G3) {
                 double ai[U], sa[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    ai[u] = conj ? -f.a[u][s].im : f.a[u][s].im;
-                    sa[u] = f.a[u][s].re + ai[u];
+                    ai[u] = conj ? -av[u][s].im : av[u][s].im;
+                    sa[u] = av[u][s].re + ai[u];
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
                     const double cr = cf[(s * NB + j) * kWave + lane];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(f.a[u][s].re, cr, acc[u][j]);
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16(av[u][s].re, cr, acc[u][j]);
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
@@ -783,14 +855,14 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 for (int j = 0; j < NB; ++j)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        acc[u][j] = mfma16(f.a[u][s].re, cr[j], acc[u][j]);
-                        acci[u][j] = mfma16(f.a[u][s].re, ci[j], acci[u][j]);
+                        acc[u][j] = mfma16(av[u][s].re, cr[j], acc[u][j]);
+                        acci[u][j] = mfma16(av[u][s].re, ci[j], acci[u][j]);
                     }
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const double ai = conj ? -f.a[u][s].im : f.a[u][s].im;
+                        const double ai = conj ? -av[u][s].im : av[u][s].im;
                         acc[u][j] = mfma16(ai, -ci[j], acc[u][j]);
                         acci[u][j] = mfma16(ai, cr[j], acci[u][j]);
                     }

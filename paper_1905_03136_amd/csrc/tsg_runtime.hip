@@ -170,7 +170,8 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
             const tsg::Variant& v = tsg::kVariants[i];
             if (g_force != v.name) continue;
             const bool serves = (v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN);
-            if (v.op == op && v.dt == (int)dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs))
+            if (v.op == op && v.dt == (int)dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs) &&
+                (!v.flatA || lda == M))
                 return &v;
         }
         return nullptr;
@@ -180,6 +181,7 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
         if (v.op != op || v.dt != (int)dt) continue;
         if (v.pairA && !a_pairs) continue;
         if (v.pairX && !x_pairs) continue;
+        if (v.flatA && lda != M) continue;
         if (v.M == M && v.N == N) return &v;
         if (v.M == 0 && !best && M <= v.maxM && N <= v.maxN && (!v.evenW || (M % 2 == 0 && N % 2 == 0)))
             best = &v;
@@ -475,7 +477,8 @@ const char* tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t
     if (M < 1 || N < 1 || M > kMaxWidth || N > kMaxWidth) return "";
     alignas(16) static const char buf16[16] = {0};
     const void* al = static_cast<const void*>(buf16);
-    const tsg::Variant* v = pick(op_kind, dt, M, N, al, M + (M & 1), al, N + (N & 1));
+    // contiguous rows (lda = M, ldb = N), 16-byte aligned operands
+    const tsg::Variant* v = pick(op_kind, dt, M, N, al, M, al, N);
     return v ? v->name : "";
 }
 

@@ -95,9 +95,10 @@ def cmd_run(args):
     db = open(args.db, "a")
     t_start = time.time()
     dtypes = set(args.dtypes.split(",")) if args.dtypes else None
+    ops = set(args.ops.split(",")) if args.ops else None
     for key in sorted(groups, key=lambda k: (k[0], k[1], k[2] * k[3])):
         op, dt, M, N = key
-        if dtypes and dt not in dtypes:
+        if (dtypes and dt not in dtypes) or (ops and op not in ops):
             continue
         cplx = dt in ("c128", "c64")
         f32 = codegen.is_f32(dt)
@@ -184,11 +185,15 @@ def write_table(db_path, out_path, merge=None):
     """Fastest correct configuration per (op, dtype, M, N) from the database;
     entries of an existing table ``merge`` that the database does not cover
     are kept."""
-    best = {}
+    from paper_1905_03136_amd.codegen import needs_layout
+    best, plain = {}, {}
     if merge and os.path.exists(merge):
         with open(merge) as f:
             for e in json.load(f).get("entries", []):
-                best[(e["op"], e["dt"], e["M"], e["N"])] = dict(e, _kept=True)
+                key = (e["op"], e["dt"], e["M"], e["N"])
+                best[key] = dict(e, _kept=True)
+                if e.get("plain_cfg"):
+                    plain[key] = dict(cfg=e["plain_cfg"], name=e.get("plain_name"), us=e.get("plain_us"), _kept=True)
     with open(db_path) as f:
         for line in f:
             try:
@@ -200,9 +205,16 @@ def write_table(db_path, out_path, merge=None):
             key = (r["op"], r["dt"], r["M"], r["N"])
             if key not in best or best[key].get("_kept") or r["us"] < best[key]["us"]:
                 best[key] = r
-    entries = [dict(op=k[0], dt=k[1], M=k[2], N=k[3], cfg=r["cfg"], name=r["name"], us=r["us"],
-                    GBps=r["GBps"], roof_frac=r["roof_frac"], K=r["K"])
-               for k, r in sorted(best.items(), key=lambda kv: (kv[0][0], kv[0][1], kv[0][2] * kv[0][3]))]
+            # fastest configuration without layout requirements on A
+            if not needs_layout(r["cfg"]) and (key not in plain or plain[key].get("_kept") or r["us"] < plain[key]["us"]):
+                plain[key] = r
+    entries = []
+    for k, r in sorted(best.items(), key=lambda kv: (kv[0][0], kv[0][1], kv[0][2] * kv[0][3])):
+        e = dict(op=k[0], dt=k[1], M=k[2], N=k[3], cfg=r["cfg"], name=r["name"], us=r["us"],
+                 GBps=r["GBps"], roof_frac=r["roof_frac"], K=r["K"])
+        if needs_layout(r["cfg"]) and k in plain:
+            e.update(plain_cfg=plain[k]["cfg"], plain_name=plain[k]["name"], plain_us=plain[k]["us"])
+        entries.append(e)
     with open(out_path, "w") as f:
         json.dump({"entries": entries}, f, indent=1)
         f.write("\n")
@@ -217,6 +229,7 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
     r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")
+    r.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
     r.add_argument("--K", type=int, default=1 << 24)
     r.add_argument("--db", default="gpurun_out/tune_db.jsonl")
     r.add_argument("--out", default=os.path.join(HERE, "tuned.json"))

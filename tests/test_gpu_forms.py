@@ -100,6 +100,17 @@ def test_precision_form_integers_exact(M, N, cplx):
     assert np.array_equal(_widen(P), oracle.tsmm(A, X))
 
 
+@pytest.mark.parametrize("K", [1, 3, 17, 65, 257, 1027])
+@pytest.mark.parametrize("M,N", [(8, 8), (16, 16), (64, 64)])
+def test_precision_form_small_K(K, M, N):
+    """Small and ragged row counts of the binary32-storage TSMM, whose kernels
+    read A as one contiguous run per wave (clamped at the end of A)."""
+    A = inputs.host_integers(K, M, 53, inputs.STREAM_A)
+    X = inputs.host_integers(M, N, 53, inputs.STREAM_C)
+    P = api.tsmm(dev(_f32(A)), dev(X)).cpu().numpy()
+    assert np.array_equal(_widen(P), oracle.tsmm(A, X))
+
+
 @pytest.mark.parametrize("M,N", [(8, 8), (32, 32), (64, 64), (13, 7)])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_precision_form_uniform(M, N, cplx):

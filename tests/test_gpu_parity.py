@@ -114,8 +114,11 @@ def test_every_square_width(w, cplx):
     assert np.array_equal(host(api.tsmm(dev(Ai), dev(Xi))), oracle.tsmm(Ai, Xi))
 
 
+# (17, 17), (18, 18), (49, 49): the TSMM reads A as one contiguous run per wave
+# (slab reads), whose last run is clamped at the end of A
 @pytest.mark.parametrize("K", [0, 1, 3, 4, 63, 64, 65, 255, 257, 1023, 4097])
-@pytest.mark.parametrize("M,N", [(1, 1), (4, 4), (8, 8), (32, 32), (64, 64), (3, 17)])
+@pytest.mark.parametrize("M,N", [(1, 1), (4, 4), (8, 8), (32, 32), (64, 64), (3, 17), (17, 17), (18, 18),
+                                 (49, 49)])
 def test_small_and_ragged_K(K, M, N):
     for cplx in (False, True):
         A = inputs.host_integers(K, M, 23, inputs.STREAM_A, cplx)
@@ -128,11 +131,12 @@ def test_small_and_ragged_K(K, M, N):
             assert np.array_equal(host(api.tsmm(dA, dev(X))), oracle.tsmm(A, X))
 
 
-@pytest.mark.parametrize("M,N", [(4, 4), (8, 8), (5, 3), (32, 32), (64, 64), (2, 2)])
+@pytest.mark.parametrize("M,N", [(4, 4), (8, 8), (5, 3), (32, 32), (64, 64), (2, 2), (17, 17), (18, 18)])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_leading_dimensions_and_canaries(M, N, cplx):
-    """Padded rows (lda > M, odd lda that defeats paired loads) give the same
-    result; padding of outputs and inputs is never written."""
+    """Padded rows (lda > M, odd lda that defeats paired loads, rows that are
+    not one contiguous run) give the same result; padding of outputs and
+    inputs is never written."""
     K = 20011
     dt = np.complex128 if cplx else np.float64
     A = inputs.host_uniform(K, M, 24, inputs.STREAM_A, cplx)
