@@ -259,6 +259,15 @@ tsg_status tsg_force_variant(const char *name);
 int32_t tsg_variant_count(void);
 const char *tsg_variant_name(int32_t i);
 
+/* tsg_set_grid_limit(blocks) caps the number of blocks of the calling thread's
+ * following TSMTTSM and TSMM launches (0 removes the cap; negative values
+ * return TSG_E_ARG).  With a small cap every block works through many tiles
+ * of a short matrix, which lets tests cover the multi-tile paths of each
+ * kernel (register rings, staging reuse) without matrices of millions of rows.
+ * Results stay within the usual bounds (TSMTTSM partial sums are folded in a
+ * different grouping, so floating-point results may differ in rounding). */
+tsg_status tsg_set_grid_limit(int32_t blocks);
+
 #ifdef __cplusplus
 }
 #endif

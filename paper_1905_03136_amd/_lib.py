@@ -38,6 +38,7 @@ PROTOTYPES = {
     "tsg_stream_read": (_i32, [_vp, _sz, _vp]),
     "tsg_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "tsg_force_variant": (_i32, [ctypes.c_char_p]),
+    "tsg_set_grid_limit": (_i32, [_i32]),
     "tsg_variant_count": (_i32, []),
     "tsg_variant_name": (ctypes.c_char_p, [_i32]),
 }
@@ -125,6 +126,10 @@ def tsg_kernel_name(op_kind, dt, conj, M, N):
 
 def tsg_force_variant(name):
     return lib().tsg_force_variant(name.encode() if name else None)
+
+
+def tsg_set_grid_limit(blocks):
+    return lib().tsg_set_grid_limit(blocks)
 
 
 def tsg_variant_count():

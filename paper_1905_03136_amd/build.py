@@ -11,6 +11,7 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -43,13 +44,56 @@ def _stale(obj, deps):
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def _compile(src, obj, extra):
-    cmd = [HIPCC, *CFLAGS, *extra, "-c", src, "-o", obj + ".tmp"]
+SPILLS = ".spills"  # per generated unit: mangled names of its kernels that spill to scratch
+
+
+def _spilled(remarks):
+    """Kernels with a non-zero scratch size in hipcc's resource-usage remarks."""
+    out, cur = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and cur and int(m.group(1)) > 0:
+            out.append(cur)
+    return out
+
+
+def _compile(src, obj, extra, resource=False):
+    flags = ["-Rpass-analysis=kernel-resource-usage"] if resource else []
+    cmd = [HIPCC, *CFLAGS, *extra, *flags, "-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stdout[-6000:]))
+    if resource:
+        with open(obj + SPILLS + ".tmp", "w") as f:
+            f.write("".join(k + "\n" for k in _spilled(r.stdout)))
+        os.replace(obj + SPILLS + ".tmp", obj + SPILLS)
     os.replace(obj + ".tmp", obj)
     return src
+
+
+def _spilled_variants(objs, variants):
+    """Names of the variants whose kernel spills registers to scratch memory
+    (from the units' resource-usage records)."""
+    from paper_1905_03136_amd import codegen
+    mangled = []
+    for o in objs:
+        if os.path.exists(o + SPILLS):
+            with open(o + SPILLS) as f:
+                mangled += [l.strip() for l in f if l.strip()]
+    if not mangled:
+        return set()
+    r = subprocess.run(["c++filt"], input="\n".join(mangled), stdout=subprocess.PIPE, text=True, check=True)
+    names = r.stdout.splitlines()
+    out = set()
+    for v in variants:
+        sym = "void " + codegen.template_of(v) + "("
+        if any(n.startswith(sym) for n in names):
+            out.add(codegen.variant_name(v))
+    return out
 
 
 def generate(widths=None, variants=None, gen_dir=GEN):
@@ -67,29 +111,45 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
     gen_dir = GEN + tag
     obj_dir = OBJ + tag
     srcs, variants = generate(widths, variants, gen_dir)
-    srcs = list(srcs) + [os.path.join(CSRC, "tsg_runtime.hip"), os.path.join(CSRC, "tsg_stream.hip"),
-                        os.path.join(CSRC, "tsg_batched.hip")]
+    table = os.path.join(gen_dir, "tsg_table.hip")
+    units = [s for s in srcs if s != table]
+    srcs = units + [os.path.join(CSRC, "tsg_runtime.hip"), os.path.join(CSRC, "tsg_stream.hip"),
+                    os.path.join(CSRC, "tsg_batched.hip")]
     OBJD = obj_dir
     os.makedirs(OBJD, exist_ok=True)
-    objs = []
-    todo = []
-    for s in srcs:
-        o = os.path.join(OBJD, os.path.basename(s) + ".o")
-        objs.append(o)
-        if _stale(o, [s] + HEADERS + [os.path.abspath(__file__)]):
-            todo.append((s, o))
+    obj_of = {s: os.path.join(OBJD, os.path.basename(s) + ".o") for s in srcs + [table]}
+    keep = set(obj_of.values())
     for o in glob.glob(os.path.join(OBJD, "*.o")):
-        if o not in objs:
+        if o not in keep:
             os.remove(o)
     jobs = jobs or min(8, os.cpu_count() or 1)
-    if todo:
+
+    def compile_all(sources, what):
+        todo = [(s, obj_of[s]) for s in sources
+                if _stale(obj_of[s], [s] + HEADERS + [os.path.abspath(__file__)])
+                or (s in units and not os.path.exists(obj_of[s] + SPILLS))]
+        if not todo:
+            return
         if verbose:
-            print("[build] compiling %d of %d units for %s (%d variants), %d jobs"
-                  % (len(todo), len(srcs), ARCH, len(variants), jobs), flush=True)
+            print("[build] compiling %d of %d %s for %s (%d variants), %d jobs"
+                  % (len(todo), len(sources), what, ARCH, len(variants), jobs), flush=True)
         with cf.ThreadPoolExecutor(jobs) as ex:
-            for done in ex.map(lambda so: _compile(so[0], so[1], list(extra_flags)), todo):
+            for done in ex.map(lambda so: _compile(so[0], so[1], list(extra_flags), so[0] in units), todo):
                 if verbose:
                     print("[build]   %s" % os.path.relpath(done, ROOT), flush=True)
+
+    # Generated units first; a variant whose kernel spills registers to
+    # scratch memory is left out of the registry (its launches would be slow,
+    # and spilled code is not trusted), then the table is compiled.
+    compile_all(srcs, "units")
+    spilled = _spilled_variants([obj_of[s] for s in units], variants)
+    if spilled:
+        print("[build] %d variant(s) spill registers and are left out of the registry: %s"
+              % (len(spilled), ", ".join(sorted(spilled))), flush=True)
+        from paper_1905_03136_amd import codegen
+        codegen.emit(gen_dir, variants, exclude=spilled)
+    compile_all([table], "registry table")
+    objs = [obj_of[s] for s in srcs] + [obj_of[table]]
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", lib_path + ".tmp", *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:

@@ -118,6 +118,55 @@ def _candidates(op, dt, M, N):
                             acc3 = mb * nb * 4 * 3
                             if cplx and acc3 <= 64 and (w == 4 or acc3 + ops <= 104):
                                 out.append(dict(c, G3=1))
+        # tails on the vector unit: full blocks on the matrix cores, the
+        # M mod 16 rows and N mod 16 columns of C as FMAs (one wave per row group)
+        rm, rn = M % 16, N % 16
+        if (rm or rn) and M > 16 and N > 16 and max(rm, rn) <= (4 if cplx else 8):
+            mb, nb = _ceil(M, 16), _ceil(N, 16)
+            mf, nf = mb - (1 if rm else 0), nb - (1 if rn else 0)
+            tails = (mb * rn + nf * rm) * cw                 # doubles of tail sums per lane
+            for g3 in ((0, 1) if cplx else (0,)):
+                acct = mf * nf * 4 * (3 if g3 else cw)       # matrix-core accumulators
+                for w in (4, 8):
+                    for u in (1, 2, 4):
+                        for nbuf in (2, 3):
+                            ops = nbuf * u * (mb + nb) * cw
+                            if ops > 72 or (nbuf > 2 and u > 2):
+                                continue
+                            if acct + ops + tails + u * cw <= (160 if w == 4 else 104):
+                                out.append(dict(kind="mfma", MB=mb, NB=nb, MW=1, U=u, WPB=w, NBUF=nbuf, TL=1,
+                                                **({"G3": 1} if g3 else {})))
+        # slab reads of A and B (rows contiguous), with or without vector tails
+        # (and, complex, with or without the three-product form)
+        if M > 8 or N > 8:
+            es = 4 if is_f32(dt) else 8                        # bytes per real storage element
+            fl = max(f for f in (1, 2, 4) if (M * cw) % f == 0 and (N * cw) % f == 0 and f * es <= 16)
+            mb, nb = _ceil(M, 16), _ceil(N, 16)
+            rm, rn = M % 16, N % 16
+            tails_ok = (rm or rn) and M > 16 and N > 16 and max(rm, rn) <= (4 if cplx else 8)
+            for tl in ((0, 1) if tails_ok else (0,)):
+                for g3 in ((0, 1) if cplx else (0,)):
+                    mf, nf = (mb - (1 if rm else 0), nb - (1 if rn else 0)) if tl else (mb, nb)
+                    acct = mf * nf * 4 * (3 if g3 else cw) + ((mb * rn + nf * rm) * cw if tl else 0)
+                    if acct > 72:
+                        continue
+                    for w in (4, 8):
+                        for u in (1, 2, 4):
+                            for nbuf in (2, 3):
+                                nl = (_ceil(4 * u * M * cw, 64 * fl) + _ceil(4 * u * N * cw, 64 * fl)) * fl * es // 8
+                                ops = nbuf * nl + u * (mb + nb) * cw
+                                lds = w * 4 * u * (M + N) * cw * es + M * N * cw * 8
+                                # (wide block grids: one wave per SIMD and two register sets only)
+                                if acct > 36 and (w > 4 or nbuf > 2):
+                                    continue
+                                if (acct + ops <= (160 if w == 4 else 104) and lds <= 64 * 1024
+                                        and (nbuf == 2 or u <= 2)):
+                                    c = dict(kind="mfma", MB=mb, NB=nb, MW=1, U=u, WPB=w, NBUF=nbuf, FL=fl)
+                                    if tl:
+                                        c["TL"] = 1
+                                    if g3:
+                                        c["G3"] = 1
+                                    out.append(c)
         return out
     if M * cw <= 8 and N * cw <= 8:
         for u in (1, 2, 4):
@@ -263,11 +312,17 @@ def exact_variants(widths, tuned=None):
                 if is_f32(dt) and (M, N) not in PRECISION:
                     continue
                 cfg = tuned.get((op, dt, M, N)) or default_config(op, dt, M, N)
-                out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=cfg))
+                cfgs = [cfg]
                 if needs_layout(cfg):
                     plain = tuned.get((op, dt, M, N, "plain")) or default_config(op, dt, M, N)
                     if not needs_layout(plain):
-                        out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=plain))
+                        cfgs.append(plain)
+                for c in cfgs:
+                    # TSMM on the matrix cores: a twin reading the old B with A
+                    # for calls with beta != 0, ahead of the one serving beta = 0
+                    if op == "tsmm" and c["kind"] == "mfma":
+                        out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=dict(c, RB=1)))
+                    out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=c))
     return out
 
 
@@ -295,6 +350,10 @@ def variant_name(v):
         tag += "_g3"
     if c.get("FL"):
         tag += "_f%d" % c["FL"]
+    if c.get("TL"):
+        tag += "_t"
+    if c.get("RB"):
+        tag += "_rb"
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -311,16 +370,17 @@ def _template(v):
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
                 M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
                 "true" if c["VB"] else "false", c["WPB"])
-        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %s, %s>" % (
+        return "tsg::tsmttsm_mfma<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), f32,
-            "true" if c.get("G3") else "false")
+            "true" if c.get("G3") else "false", "true" if c.get("TL") else "false", c.get("FL", 0))
     if c["kind"] == "valu":
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s, %d>" % (
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s, %d, %s>" % (
         M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false",
-        c.get("OCC", 1), f32, "true" if c.get("G3") else "false", c.get("FL", 0))
+        c.get("OCC", 1), f32, "true" if c.get("G3") else "false", c.get("FL", 0),
+        "true" if c.get("RB") else "false")
 
 
 def rows_per_tile(v):
@@ -349,20 +409,26 @@ def _launcher(v, fn):
 
 def _record(v, fn):
     c = v["cfg"]
-    pair_a = int(c["kind"] in ("valu", "mfma") and (bool(c.get("VA")) or c.get("FL", 0) >= 2))
-    pair_x = int(c["kind"] == "valu" and bool(c.get("VB")))
+    # slab reads need 16-byte alignment (and, with lda = M, an even width) where
+    # one lane load spans two or more elements (a complex element is two reals)
+    slab_pairs = c.get("FL", 0) // (2 if DTYPES[v["dt"]][1] else 1) >= 2
+    pair_a = int(c["kind"] in ("valu", "mfma") and (bool(c.get("VA")) or slab_pairs))
+    pair_x = int((c["kind"] == "valu" and bool(c.get("VB"))) or (v["op"] == "tsmttsm" and slab_pairs))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)
     flat_a = int(bool(c.get("FL")))
-    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
+    read_b = int(bool(c.get("RB")))
+    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
             % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
-               64 * c["WPB"], rows_per_tile(v), pack, flat_a, variant_name(v), fn.replace("launch_", "kernel_"), fn))
+               64 * c["WPB"], rows_per_tile(v), pack, flat_a, read_b, variant_name(v),
+               fn.replace("launch_", "kernel_"), fn))
 
 
-def emit(outdir, variants, per_file=6):
+def emit(outdir, variants, per_file=6, exclude=()):
     """Write gen/tsg_gen_XX.hip (instantiations + launchers) and gen/tsg_table.hip.
     Returns the list of written source files.  Files are only rewritten when
-    their text changes, so unchanged units need no recompilation."""
+    their text changes, so unchanged units need no recompilation.  Variants
+    named in ``exclude`` are compiled but left out of the registry table."""
     os.makedirs(outdir, exist_ok=True)
     files = []
     recs = []
@@ -376,7 +442,8 @@ def emit(outdir, variants, per_file=6):
             fn = "launch_%s" % variant_name(v)
             body.append(_launcher(v, fn))
             decls.append("void %s(const tsg::Launch& p);\nconst void* %s();\n" % (fn, fn.replace("launch_", "kernel_")))
-            recs.append((v, fn))
+            if variant_name(v) not in exclude:
+                recs.append((v, fn))
         body.append("}  // namespace tsg_gen\n")
         text = "".join(body)
         path = os.path.join(outdir, "tsg_gen_%02d.hip" % fi)
@@ -419,6 +486,11 @@ def all_variants(widths=None, tuned_path=None):
             seen.add((M, N))
             uniq.append((M, N))
     return exact_variants(uniq, load_tuned(tuned_path)) + generic_variants()
+
+
+def template_of(v):
+    """C++ name of the kernel template instantiation of variant ``v``."""
+    return _template(v)
 
 
 def kernel_symbol(name, tuned=None):

@@ -29,6 +29,133 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Value of lane 16 (l / 16) + c for lane l: the DPP row broadcast
+// (row_newbcast) of one lane of every row of 16 lanes, two 32-bit moves per
+// double.  c must fold to a constant (the DPP control is an immediate).
+template <int C_>
+__device__ __forceinline__ double row_bcast_c(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + C_, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + C_, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_bcast(double v, int c)
+{
+    switch (c) {
+    case 0: return row_bcast_c<0>(v);
+    case 1: return row_bcast_c<1>(v);
+    case 2: return row_bcast_c<2>(v);
+    case 3: return row_bcast_c<3>(v);
+    case 4: return row_bcast_c<4>(v);
+    case 5: return row_bcast_c<5>(v);
+    case 6: return row_bcast_c<6>(v);
+    case 7: return row_bcast_c<7>(v);
+    case 8: return row_bcast_c<8>(v);
+    case 9: return row_bcast_c<9>(v);
+    case 10: return row_bcast_c<10>(v);
+    case 11: return row_bcast_c<11>(v);
+    case 12: return row_bcast_c<12>(v);
+    case 13: return row_bcast_c<13>(v);
+    case 14: return row_bcast_c<14>(v);
+    default: return row_bcast_c<15>(v);
+    }
+}
+__device__ __forceinline__ zd row_bcast(zd v, int c) { return zd{row_bcast(v.re, c), row_bcast(v.im, c)}; }
+
+// acc += op(a) b for the VALU tail strips (op = conjugate when conj).
+__device__ __forceinline__ void fma_tail(double& acc, double a, double b, int) { acc = __builtin_fma(a, b, acc); }
+__device__ __forceinline__ void fma_tail(zd& acc, zd a, zd b, int conj)
+{
+    const double ai = conj ? -a.im : a.im;
+    acc.re = __builtin_fma(a.re, b.re, __builtin_fma(-ai, b.im, acc.re));
+    acc.im = __builtin_fma(a.re, b.im, __builtin_fma(ai, b.re, acc.im));
+}
+
+// Sum over the four k-slots (lanes l, l ^ 16, l ^ 32, l ^ 48), fixed order.
+__device__ __forceinline__ double slot_sum(double v)
+{
+    v += __shfl_xor(v, 16, kWave);
+    return v + __shfl_xor(v, 32, kWave);
+}
+__device__ __forceinline__ zd slot_sum(zd v) { return zd{slot_sum(v.re), slot_sum(v.im)}; }
+
+// ---------------------------------------------------------- slab reads
+// Where the rows of a tall matrix are contiguous (ld = width), the rows a wave
+// consumes in one tile are one contiguous run; slab reads load that run with
+// consecutive loads of FL storage elements per lane (one contiguous piece of
+// up to 1 KB per load instruction, whatever the width), store it in the
+// wave's own LDS region and read the matrix-core operands back from there.
+// Registers of one tile: per-row fragments, or the lane's share of the run.
+template <class T, int U, int MS>
+struct row_regs {
+    T a[U][MS];
+};
+template <class SV, int NL>
+struct slab_regs {
+    SV v[NL];
+};
+typedef float flt4 __attribute__((ext_vector_type(4)));
+template <class S, int FL>
+struct slab_vec;
+template <>
+struct slab_vec<double, 1> { typedef double type; };
+template <>
+struct slab_vec<double, 2> { typedef dbl2 type; };
+template <>
+struct slab_vec<float, 1> { typedef float type; };
+template <>
+struct slab_vec<float, 2> { typedef flt2 type; };
+template <>
+struct slab_vec<float, 4> { typedef flt4 type; };
+// real type of a storage element (complex elements are two of them)
+template <class S>
+struct real_of { typedef S type; };
+template <>
+struct real_of<zd> { typedef double type; };
+template <>
+struct real_of<zf> { typedef float type; };
+// element idx of a run staged in LDS, widened to binary64
+__device__ __forceinline__ double lds_elem(const double* p, int idx, double) { return p[idx]; }
+__device__ __forceinline__ double lds_elem(const float* p, int idx, double) { return (double)p[idx]; }
+__device__ __forceinline__ zd lds_elem(const double* p, int idx, zd) { return zd{p[2 * idx], p[2 * idx + 1]}; }
+__device__ __forceinline__ zd lds_elem(const float* p, int idx, zd)
+{
+    return zd{(double)p[2 * idx], (double)p[2 * idx + 1]};
+}
+
+// Load the lane's share of a run of n elements starting at element e0 of a
+// matrix of `total` elements: load i covers elements e0 + (64 i + lane) FL ..;
+// positions past the end are clamped to the last FL elements (total is a
+// multiple of FL), their values are never used.
+template <int FL, int NL, class SR, class SV>
+__device__ __forceinline__ void slab_load(const SR* p, int64_t e0, int64_t total, int lane, SV (&v)[NL])
+{
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int64_t e = e0 + (int64_t)(i * kWave + lane) * FL;
+        const int64_t ec = e <= total - FL ? e : total - FL;
+        v[i] = __builtin_nontemporal_load(reinterpret_cast<const SV*>(p + ec));
+    }
+}
+// Store the lane's share (n elements of the run) into the wave's LDS region.
+// The lanes then read each other's elements.  The hardware completes one
+// wave's LDS accesses in order, so no barrier instruction is needed, but the
+// compiler must see the exchange: without a memory barrier it may treat a
+// lane's read as independent of the other lanes' writes, keep the value read
+// for the previous tile, and move the read under the lane mask of the
+// conditional write (observed: lanes past the run's end then used stale
+// operands).  The empty asm with a memory clobber is that barrier.
+template <int FL, int NL, int n, class SR, class SV>
+__device__ __forceinline__ void slab_put(SR* lds, int lane, const SV (&v)[NL])
+{
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int o = (i * kWave + lane) * FL;
+        if (i + 1 < NL || o < n) *reinterpret_cast<SV*>(lds + o) = v[i];
+    }
+    __asm__ volatile("" ::: "memory");
+}
+
 // Element (m, n) of TSMM's small operand op(C): opc 0 reads C(m, n) = C[m ldc + n];
 // opc 1 (transpose) and 2 (conjugate transpose, the caller negates the
 // imaginary part) read C[n ldc + m] of a stored N x M matrix.
@@ -68,9 +195,26 @@ __device__ __forceinline__ int64_t small_index(int m, int n, int64_t ldc, int op
 //
 // Output layout of the 16x16 FP64 accumulator (checked on gfx950 with an
 // in-bounds probe): lane l, element r holds D(l / 16 + 4 r, l % 16).
+//
+// TL (tails on the vector unit; compile-time widths, MW = 1): where M or N is
+// not a multiple of 16, a padded 16-wide block would spend a whole row or
+// column of matrix-core products on RM = M mod 16 (RN = N mod 16) useful
+// rows, and these kernels are bound by the matrix cores there.  With TL only
+// the full blocks go to the matrix cores; the column strip C(:, N - RN ..) and
+// the row strip C(M - RM .., full columns) are vector FMAs: lane (q, i) of a
+// k-slot q multiplies its A(k, 16 b + i) by B(k, N - RN + c), broadcast from
+// lane c of its row of 16 lanes, and its B(k, 16 b + i) by A(k, M - RM + r)
+// likewise, keeping (M_blocks RN + N_full RM) partial sums per lane, which
+// the epilogue sums over the four k-slots.
+//
+// FL (slab reads; lda = M, ldb = N, compile-time widths whose rows are a
+// multiple of FL real elements, MW = 1): the 4U rows of a wave are read as
+// two contiguous runs (see slab_load), staged in the wave's LDS region, and
+// the fragments above are read from there; at widths whose rows are not
+// whole 128-byte lines the per-row fragment loads touch more lines per load.
 // ============================================================================
 template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1,
-          bool F32 = false, bool G3 = false>
+          bool F32 = false, bool G3 = false, bool TL = false, int FL = 0>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
              const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
@@ -83,6 +227,14 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
     constexpr int RT = 4 * U * RG;
     constexpr int EMAX = (MC ? MC : MW * MB * 16) * (NC ? NC : NB * 16) * CW;
     static_assert(WPB % MW == 0, "waves must split evenly");
+    static_assert(!TL || (MC > 0 && NC > 0 && MW == 1 && MB == (MC + 15) / 16 && NB == (NC + 15) / 16),
+                  "vector tails: compile-time widths, one wave per row group");
+    static_assert(FL == 0 || (MW == 1 && MC > 0 && NC > 0 && (MC * CW) % FL == 0 && (NC * CW) % FL == 0),
+                  "slab reads: compile-time widths whose rows are multiples of FL, one wave per row group");
+    constexpr int RM = TL ? MC % 16 : 0;        // rows of C in the row strip
+    constexpr int RN = TL ? NC % 16 : 0;        // columns of C in the column strip
+    constexpr int MF = MB - (RM ? 1 : 0);       // m-blocks on the matrix cores
+    constexpr int NF = NB - (RN ? 1 : 0);       // n-blocks on the matrix cores
     __shared__ double part[EMAX];
 
     const S* __restrict__ A = static_cast<const S*>(Av);
@@ -96,10 +248,12 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
     const int lr = lane >> 4;
     const int lc = lane & 15;
 
-    // Column guards.  Where a compile-time width covers every column a lane can
-    // address, the guard is the constant true: a guard the compiler cannot
-    // prove true makes it turn the guarded load into a branch, and the loop
-    // then waits for every load in flight at each tile.
+    // Column offsets.  A lane whose column lies past the width reads a valid
+    // element of the same row instead (column 0); such values only reach
+    // entries of C past M or N, which are never stored, so they need no
+    // zeroing (rows past K are zeroed: they would reach every entry).  Where
+    // a compile-time width covers every column a lane can address, the test
+    // is the constant true and the offset is the plain column.
     int moff[MB], noff[NB];
     bool mok[MB], nok[NB];
 #pragma unroll
@@ -127,13 +281,46 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             if constexpr (CPLX) acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
             if constexpr (G3) accs[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
+    // TL: tc[b][c] sums A(k, 16 b + lc) B(k, NF 16 + c), tr[b][r] sums A(k, MF 16 + r) B(k, 16 b + lc)
+    static_assert(!TL || (MF >= 1 && NF >= 1), "vector tails serve widths above 16");
+    T tc[RN ? MB : 1][RN ? RN : 1];
+    T tr[RM ? NF : 1][RM ? RM : 1];
+#pragma unroll
+    for (int i = 0; i < (RN ? MB : 1); ++i)
+#pragma unroll
+        for (int c = 0; c < (RN ? RN : 1); ++c) tc[i][c] = zero_of<T>();
+#pragma unroll
+    for (int j = 0; j < (RM ? NF : 1); ++j)
+#pragma unroll
+        for (int r = 0; r < (RM ? RM : 1); ++r) tr[j][r] = zero_of<T>();
 
-    struct Frag {
+    // FL (slab reads, real data, lda = M and ldb = N): the 4U rows of a wave
+    // are runs of 4U M elements of A and 4U N elements of B
+    constexpr int SLA = FL ? 4 * U * MC * CW : 0, SLB = FL ? 4 * U * NC * CW : 0;  // real elements
+    constexpr int NLA = FL ? (SLA + kWave * FL - 1) / (kWave * FL) : 1;
+    constexpr int NLB = FL ? (SLB + kWave * FL - 1) / (kWave * FL) : 1;
+    using SR = typename real_of<S>::type;                         // real storage type (slab reads)
+    using SV = typename slab_vec<SR, FL ? FL : 1>::type;          // one slab load of a lane
+    __shared__ __attribute__((aligned(16))) SR slab[FL ? WPB * (SLA + SLB) : 1];
+    SR* const mya = slab + (FL ? wave * (SLA + SLB) : 0);
+    SR* const myb = mya + SLA;
+
+    struct RowFrag {
         T a[U][MB];
         T b[U][NB];
     };
+    struct SlabFrag {
+        SV a[NLA];
+        SV b[NLB];
+    };
+    using Frag = typename std::conditional<FL != 0, SlabFrag, RowFrag>::type;
     Frag fr[NBUF];
     auto load = [&](int64_t t, Frag& f) {
+        if constexpr (FL) {
+            const int64_t r0 = t * RT + (int64_t)rg * U * 4;
+            slab_load<FL, NLA>(reinterpret_cast<const SR*>(A), r0 * MC * CW, K * (int64_t)(MC * CW), lane, f.a);
+            slab_load<FL, NLB>(reinterpret_cast<const SR*>(B), r0 * NC * CW, K * (int64_t)(NC * CW), lane, f.b);
+        } else {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = t * RT + (int64_t)(rg * U + u) * 4 + lr;
@@ -142,70 +329,114 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             const S* ar = A + rc * lda;
             const S* br = B + rc * ldb;
 #pragma unroll
-            for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok & mok[i], ld_stream(ar + moff[i]));
+            for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok, ld_stream(ar + moff[i]));
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 // with MW > 1 the waves of a row group read the same B: keep it in cache
                 if constexpr (MW > 1)
-                    f.b[u][j] = keep(ok & nok[j], ld_shared(br + noff[j]));
+                    f.b[u][j] = keep(ok, ld_shared(br + noff[j]));
                 else
-                    f.b[u][j] = keep(ok & nok[j], ld_stream(br + noff[j]));
+                    f.b[u][j] = keep(ok, ld_stream(br + noff[j]));
             }
         }
+        }
     };
-    auto compute = [&](int64_t, Frag& f) {
+    auto compute = [&](int64_t t, Frag& f) {
+        // matrix-core operands of the tile (from LDS with slab reads; rows past K are zero)
+        T av[U][MB], bv[U][NB];
+        if constexpr (FL) {
+            slab_put<FL, NLA, SLA>(mya, lane, f.a);
+            slab_put<FL, NLB, SLB>(myb, lane, f.b);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = t * RT + (int64_t)(rg * U + u) * 4 + lr < K;
+#pragma unroll
+                for (int i = 0; i < MB; ++i) av[u][i] = keep(ok, lds_elem(mya, (4 * u + lr) * MC + moff[i], T{}));
+#pragma unroll
+                for (int j = 0; j < NB; ++j) bv[u][j] = keep(ok, lds_elem(myb, (4 * u + lr) * NC + noff[j], T{}));
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i) av[u][i] = f.a[u][i];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) bv[u][j] = f.b[u][j];
+            }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            // matrix cores: blocks i < MF, j < NF (all blocks without TL)
             if constexpr (!CPLX) {
 #pragma unroll
-                for (int i = 0; i < MB; ++i)
+                for (int i = 0; i < MF; ++i)
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i], f.b[u][j], acc[i][j]);
+                    for (int j = 0; j < NF; ++j) acc[i][j] = mfma16(av[u][i], bv[u][j], acc[i][j]);
             } else if constexpr (G3) {
                 // three passes over all blocks, so the updates of one
-                // accumulator are MB NB instructions apart
-                double ai[MB], sa[MB], sb[NB];
+                // accumulator are MF NF instructions apart; the sums
+                // Ar + Ai and Br + Bi are formed just before the pass that
+                // uses them (fewer values live at once)
+                double ai[MB];
 #pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    ai[i] = conj ? -f.a[u][i].im : f.a[u][i].im;
-                    sa[i] = f.a[u][i].re + ai[i];
+                for (int i = 0; i < MF; ++i) ai[i] = conj ? -av[u][i].im : av[u][i].im;
+#pragma unroll
+                for (int i = 0; i < MF; ++i)
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) acc[i][j] = mfma16(av[u][i].re, bv[u][j].re, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < MF; ++i)
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) acci[i][j] = mfma16(ai[i], bv[u][j].im, acci[i][j]);
+#pragma unroll
+                for (int i = 0; i < MF; ++i) ai[i] += av[u][i].re;  // Ar + Ai
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const double sb = bv[u][j].re + bv[u][j].im;
+#pragma unroll
+                    for (int i = 0; i < MF; ++i) accs[i][j] = mfma16(ai[i], sb, accs[i][j]);
                 }
-#pragma unroll
-                for (int j = 0; j < NB; ++j) sb[j] = f.b[u][j].re + f.b[u][j].im;
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(f.a[u][i].re, f.b[u][j].re, acc[i][j]);
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) acci[i][j] = mfma16(ai[i], f.b[u][j].im, acci[i][j]);
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) accs[i][j] = mfma16(sa[i], sb[j], accs[i][j]);
             } else {
                 // All products with Re(a) first, then those with Im(a): the two
-                // updates of one accumulator are 2 MB NB instructions apart
+                // updates of one accumulator are 2 MF NF instructions apart
                 // instead of back to back.
                 double nbi[NB];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) nbi[j] = -f.b[u][j].im;
+                for (int j = 0; j < NF; ++j) nbi[j] = -bv[u][j].im;
 #pragma unroll
-                for (int i = 0; i < MB; ++i)
+                for (int i = 0; i < MF; ++i)
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) {
-                        acc[i][j] = mfma16(f.a[u][i].re, f.b[u][j].re, acc[i][j]);
-                        acci[i][j] = mfma16(f.a[u][i].re, f.b[u][j].im, acci[i][j]);
+                    for (int j = 0; j < NF; ++j) {
+                        acc[i][j] = mfma16(av[u][i].re, bv[u][j].re, acc[i][j]);
+                        acci[i][j] = mfma16(av[u][i].re, bv[u][j].im, acci[i][j]);
                     }
 #pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    const double ai = conj ? -f.a[u][i].im : f.a[u][i].im;
+                for (int i = 0; i < MF; ++i) {
+                    const double ai = conj ? -av[u][i].im : av[u][i].im;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) {
+                    for (int j = 0; j < NF; ++j) {
                         acc[i][j] = mfma16(ai, nbi[j], acc[i][j]);
-                        acci[i][j] = mfma16(ai, f.b[u][j].re, acci[i][j]);
+                        acci[i][j] = mfma16(ai, bv[u][j].re, acci[i][j]);
                     }
+                }
+            }
+            // vector unit: the column strip (all m-blocks, including the
+            // partial one, times the broadcast tail columns of B) and the row
+            // strip (broadcast tail rows of A times the full n-blocks of B)
+            if constexpr (RN > 0) {
+#pragma unroll
+                for (int c = 0; c < RN; ++c) {
+                    const T bc = row_bcast(bv[u][NB - 1], c);
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) fma_tail(tc[i][c], av[u][i], bc, conj);
+                }
+            }
+            if constexpr (RM > 0) {
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    const T ar = row_bcast(av[u][MB - 1], r);
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) fma_tail(tr[j][r], ar, bv[u][j], conj);
                 }
             }
         }
@@ -224,14 +455,32 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
             }
     }
 
+    // TL: sum the tail strips over the four k-slots (every lane gets the sum)
+#pragma unroll
+    for (int i = 0; i < (RN ? MB : 0); ++i)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) tc[i][c] = slot_sum(tc[i][c]);
+#pragma unroll
+    for (int j = 0; j < (RM ? NF : 0); ++j)
+#pragma unroll
+        for (int r = 0; r < RM; ++r) tr[j][r] = slot_sum(tr[j][r]);
+
     // Fold the row groups into the block partial, one group after the other.
     const int E = M * N * CW;
+    auto put = [&](int g, int e, T v) {
+        if constexpr (CPLX) {
+            part[e] = (g == 0) ? v.re : part[e] + v.re;
+            part[e + 1] = (g == 0) ? v.im : part[e + 1] + v.im;
+        } else {
+            part[e] = (g == 0) ? v : part[e] + v;
+        }
+    };
     for (int g = 0; g < RG; ++g) {
         if (rg == g) {
 #pragma unroll
-            for (int i = 0; i < MB; ++i)
+            for (int i = 0; i < MF; ++i)
 #pragma unroll
-                for (int j = 0; j < NB; ++j)
+                for (int j = 0; j < NF; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int m = (mw * MB + i) * 16 + lr + 4 * r;
@@ -242,6 +491,19 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
                             if constexpr (CPLX) part[e + 1] = (g == 0) ? acci[i][j][r] : part[e + 1] + acci[i][j][r];
                         }
                     }
+            if (lr == 0) {
+#pragma unroll
+                for (int i = 0; i < (RN ? MB : 0); ++i)
+#pragma unroll
+                    for (int c = 0; c < RN; ++c) {
+                        const int m = i * 16 + lc;
+                        if (m < M) put(g, (m * N + NF * 16 + c) * CW, tc[i][c]);
+                    }
+#pragma unroll
+                for (int j = 0; j < (RM ? NF : 0); ++j)
+#pragma unroll
+                    for (int r = 0; r < RM; ++r) put(g, ((MF * 16 + r) * N + j * 16 + lc) * CW, tr[j][r]);
+            }
         }
         __syncthreads();
     }
@@ -634,32 +896,8 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // rows l/16 + 4r (r < 4) of column l%16 of each 16 x 16 output block: sixteen
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
-// Registers of one tile of A: per-row fragments, or (slab reads) the lane's
-// share of the wave's contiguous slab, FL storage elements per load.
-template <class T, int U, int MS>
-struct row_regs {
-    T a[U][MS];
-};
-template <class SV, int NL>
-struct slab_regs {
-    SV v[NL];
-};
-typedef float flt4 __attribute__((ext_vector_type(4)));
-template <class S, int FL>
-struct slab_vec;
-template <>
-struct slab_vec<double, 1> { typedef double type; };
-template <>
-struct slab_vec<double, 2> { typedef dbl2 type; };
-template <>
-struct slab_vec<float, 1> { typedef float type; };
-template <>
-struct slab_vec<float, 2> { typedef flt2 type; };
-template <>
-struct slab_vec<float, 4> { typedef flt4 type; };
-
 template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1,
-          bool F32 = false, bool G3 = false, int FL = 0>
+          bool F32 = false, bool G3 = false, int FL = 0, bool RB = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
@@ -691,7 +929,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int NFRAG = MS * NB * kWave;
     constexpr int SLAB = FL ? 16 * U * MC : 0;               // elements of A per wave and tile
     constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
-    using SR = typename std::conditional<CPLX, double, S>::type;  // real storage type (slab reads)
+    using SR = typename real_of<S>::type;                         // real storage type (slab reads)
     using SV = typename slab_vec<SR, FL ? FL : 1>::type;          // one slab load of a lane
     __shared__ double cf[NFRAG * (G3 ? 3 : CW)];
     __shared__ __attribute__((aligned(16))) SR slab[FL ? WPB * SLAB : 1];
@@ -737,23 +975,39 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         koff[s] = kok[s] ? m : 0;
     }
 
-    using Frag = typename std::conditional<FL != 0, slab_regs<SV, NL>, row_regs<T, U, MS>>::type;
+    // RB (calls with beta != 0): the old values of the tile's B are loaded with
+    // its A, in the same register ring, so a store never waits for its own
+    // read (the run-time beta path reads them one by one before each store).
+    using ARegs = typename std::conditional<FL != 0, slab_regs<SV, NL>, row_regs<T, U, MS>>::type;
+    struct Frag : ARegs {
+        T ob[RB ? U : 1][RB ? NB : 1][4];
+    };
     Frag fr[NBUF];
     const int64_t KM = K * (int64_t)M;  // slab reads: elements of A
     SR* const mine = slab + (FL ? wave * SLAB : 0);
     auto load = [&](int64_t t, Frag& f) {
+        if constexpr (RB) {
+            // old B at the positions this lane stores (clamped into B; values
+            // of rows past K or columns past N are never used)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lr + 4 * r;
+                        const int n = 16 * j + lc;
+                        const int64_t rc = row < K ? row : K - 1;
+                        const int nc = n < N ? n : N - 1;
+                        f.ob[u][j][r] = ld_stream(B + rc * ldb + nc);
+                    }
+        }
         if constexpr (FL) {
             // the wave's run starts at row t RT + 16 U wave; positions past
             // the end of A are clamped to its last FL elements (K M is a
             // multiple of FL), their rows are never stored
             const int64_t base = (t * RT + (int64_t)wave * U * 16) * MC;
-            const SR* As = reinterpret_cast<const SR*>(A);
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int64_t e = base + (int64_t)(i * kWave + lane) * FL;
-                const int64_t ec = e <= KM - FL ? e : KM - FL;
-                f.v[i] = __builtin_nontemporal_load(reinterpret_cast<const SV*>(As + ec));
-            }
+            slab_load<FL, NL>(reinterpret_cast<const SR*>(A), base, KM, lane, f.v);
             return;
         } else {
 #pragma unroll
@@ -781,11 +1035,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         __asm__ volatile("" ::: "memory");
         T av[U][MS];  // matrix-core A operands of the tile
         if constexpr (FL) {
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const int o = (i * kWave + lane) * FL;
-                if (i + 1 < NL || o < SLAB) *reinterpret_cast<SV*>(mine + o) = f.v[i];
-            }
+            slab_put<FL, NL, SLAB>(mine, lane, f.v);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -894,12 +1144,19 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                             S* p = B + row * ldb + n;
                             if constexpr (!CPLX) {
                                 double v = alpha * acc[u][j][r];
-                                if (read_b) v = __builtin_fma(beta, ld_plain(p), v);
+                                if constexpr (RB)
+                                    v = __builtin_fma(beta, f.ob[u][j][r], v);
+                                else if (read_b)
+                                    v = __builtin_fma(beta, ld_plain(p), v);
                                 st_out<kStream>(p, v);
                             } else {
                                 zd v = zd{alpha * acc[u][j][r], alpha * acci[u][j][r]};
-                                if (read_b) {
-                                    const zd o = ld_plain(p);
+                                if (RB || read_b) {
+                                    zd o;
+                                    if constexpr (RB)
+                                        o = f.ob[u][j][r];
+                                    else
+                                        o = ld_plain(p);
                                     v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
                                 }
                                 st_out<kStream>(p, v);

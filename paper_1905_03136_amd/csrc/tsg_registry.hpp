@@ -39,7 +39,8 @@ struct Variant {
     int threads;        // block size
     int rows_per_tile;  // rows consumed by one block per grid-stride iteration (for P = 1)
     int pack;           // row packing: 0 none, 1 P = 16 / max(M, N) (TSMTTSM), 2 P = 16 / N (TSMM)
-    int flatA;          // reads A as one run of rows: needs lda == M
+    int flatA;          // reads the tall operands as runs of rows: needs lda == M (TSMTTSM: and ldb == N)
+    int readB;          // TSMM reading the old B with A (serves only calls with beta != 0)
     const char* name;
     const void* (*kernel)(); // device function, for occupancy queries
     void (*launch)(const Launch&);

@@ -64,6 +64,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local std::string g_force;  // variant forced by tsg_force_variant ("" = automatic choice)
+thread_local int g_grid_cap = 0;   // block cap set by tsg_set_grid_limit (0 = none)
 
 tsg_status fail(tsg_status s, const char* fmt, ...)
 {
@@ -160,10 +161,12 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 // Choose the variant: the exact (op, dtype, M, N) one if its access
 // requirements hold, else the first run-time-width variant covering (M, N).
 const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int64_t lda, const void* X,
-                         int64_t ldx)
+                         int64_t ldx, bool beta_nz = false)
 {
     const bool a_pairs = (lda % 2 == 0) && aligned(A, 16);
     const bool x_pairs = (ldx % 2 == 0) && aligned(X, 16);
+    // slab reads: the rows of A (TSMTTSM: and of B) are one contiguous run
+    const bool rows_contiguous = lda == M && (op != tsg::OP_TSMTTSM || ldx == N);
     const tsg::Variant* best = nullptr;
     if (!g_force.empty()) {
         for (int i = 0; i < tsg::kNumVariants; ++i) {
@@ -171,7 +174,7 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
             if (g_force != v.name) continue;
             const bool serves = (v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN);
             if (v.op == op && v.dt == (int)dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs) &&
-                (!v.flatA || lda == M))
+                (!v.flatA || rows_contiguous) && (!v.readB || beta_nz))
                 return &v;
         }
         return nullptr;
@@ -181,7 +184,8 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
         if (v.op != op || v.dt != (int)dt) continue;
         if (v.pairA && !a_pairs) continue;
         if (v.pairX && !x_pairs) continue;
-        if (v.flatA && lda != M) continue;
+        if (v.flatA && !rows_contiguous) continue;
+        if (v.readB && !beta_nz) continue;
         if (v.M == M && v.N == N) return &v;
         if (v.M == 0 && !best && M <= v.maxM && N <= v.maxN && (!v.evenW || (M % 2 == 0 && N % 2 == 0)))
             best = &v;
@@ -261,6 +265,7 @@ int grid_for(int dev, const tsg::Variant& v, int64_t K, int M, int N, int cus)
     const int64_t tiles = (K + rows - 1) / rows;
     const int64_t cap = (int64_t)cus * occupancy(dev, v);
     int64_t g = tiles < cap ? tiles : cap;
+    if (g_grid_cap > 0 && g > g_grid_cap) g = g_grid_cap;
     return g < 1 ? 1 : (int)g;
 }
 
@@ -345,7 +350,7 @@ tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32
     if ((s = current_device(&dev)) != TSG_OK) return s;
     DeviceInfo di;
     if ((s = device_info(dev, &di)) != TSG_OK) return s;
-    const tsg::Variant* v = pick(tsg::OP_TSMM, dt, M, N, A, lda, B, ldb);
+    const tsg::Variant* v = pick(tsg::OP_TSMM, dt, M, N, A, lda, B, ldb, beta != 0.0);
     if (!v) return fail(TSG_E_UNSUPPORTED, "no kernel variant for TSMM %dx%d%s", M, N,
                         g_force.empty() ? "" : " (a forced variant does not apply)");
     tsg::Launch p{};
@@ -464,6 +469,14 @@ tsg_status tsg_force_variant(const char* name)
             return TSG_OK;
         }
     return fail(TSG_E_ARG, "no kernel variant named %s", name);
+}
+
+tsg_status tsg_set_grid_limit(int32_t blocks)
+{
+    g_err.clear();
+    if (blocks < 0) return fail(TSG_E_ARG, "grid limit %d < 0", blocks);
+    g_grid_cap = blocks;
+    return TSG_OK;
 }
 
 int32_t tsg_variant_count(void) { return tsg::kNumVariants; }

@@ -28,10 +28,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def source_hash():
-    """Hash of everything that decides which kernel code runs: device and
-    runtime sources, the code generator and the tuned table."""
+    """Hash of everything that decides which code the TSMTTSM / TSMM calls
+    run: their kernel templates and device helpers, the runtime (variant
+    choice, grid sizing), the code generator and the tuned table.  The batched
+    form and the bandwidth probes have sources of their own and are not part
+    of it."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.hpp")))
+    files = sorted(f for f in glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.hpp"))
+                   if os.path.basename(f) not in ("tsg_batched.hip", "tsg_stream.hip"))
     files += [os.path.join(HERE, "codegen.py"), os.path.join(HERE, "tuned.json")]
     for f in files:
         h.update(os.path.basename(f).encode())

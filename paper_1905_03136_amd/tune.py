@@ -49,6 +49,11 @@ def cmd_build(args):
     sys.path.insert(0, ROOT)
     from paper_1905_03136_amd import build, codegen
     variants = codegen.tuning_variants(_widths(args.widths))
+    ops = set(args.ops.split(",")) if args.ops else None
+    dtypes = set(args.dtypes.split(",")) if args.dtypes else None
+    # exact-width candidates of the selected operations and dtypes (run-time-width variants always)
+    variants = [v for v in variants if v["M"] == 0 or
+                ((not ops or v["op"] in ops) and (not dtypes or v["dt"] in dtypes))]
     build.build(variants=variants, lib_path=TUNE_LIB, tag="_tune")
 
 
@@ -226,6 +231,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     b = sub.add_parser("build")
     b.add_argument("--widths", default="graded")
+    b.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
+    b.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
     r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")

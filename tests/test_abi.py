@@ -100,6 +100,13 @@ def test_kernel_names_cover_all_widths(lib):
     assert _lib.tsg_kernel_name(0, 0, 0, 65, 1) == ""
 
 
+def test_grid_limit_hook(lib):
+    assert _lib.tsg_set_grid_limit(-1) == _lib.TSG_E_ARG
+    assert "grid limit" in _lib.tsg_last_error()
+    assert _lib.tsg_set_grid_limit(5) == _lib.TSG_OK
+    assert _lib.tsg_set_grid_limit(0) == _lib.TSG_OK
+
+
 def test_precision_dtypes_validated(lib):
     # binary32 storage: 4-byte (real) / 8-byte (complex) alignment of A and B, C stays binary64
     assert _lib.tsg_tsmttsm(_lib.TSG_R32, 0, 10, 4, 4, A + 4, 4, A, 4, A, 4, None) != _lib.TSG_E_ARG

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1905_03136_amd import api, inputs
+from paper_1905_03136_amd import _lib, api, inputs
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -110,8 +110,25 @@ def test_every_square_width(w, cplx):
     Ai = inputs.host_integers(K, w, 24, inputs.STREAM_A, cplx)
     Bi = inputs.host_integers(K, w, 24, inputs.STREAM_B, cplx)
     Xi = inputs.host_integers(w, w, 24, inputs.STREAM_C, cplx)
-    assert np.array_equal(host(api.tsmttsm(dev(Ai), dev(Bi))), oracle.tsmttsm(Ai, Bi))
-    assert np.array_equal(host(api.tsmm(dev(Ai), dev(Xi))), oracle.tsmm(Ai, Xi))
+    Ci, Pi = oracle.tsmttsm(Ai, Bi), oracle.tsmm(Ai, Xi)
+    Ui = oracle.tsmm(Ai, Xi, Bi.copy(), alpha=-1.0, beta=1.0)    # update form B - A C
+
+    def update():
+        dB = dev(Bi)
+        api.tsmm(dev(Ai), dev(Xi), out=dB, alpha=-1.0, beta=1.0)
+        return host(dB)
+    assert np.array_equal(host(api.tsmttsm(dev(Ai), dev(Bi))), Ci)
+    assert np.array_equal(host(api.tsmm(dev(Ai), dev(Xi))), Pi)
+    assert np.array_equal(update(), Ui)
+    # three blocks: each block works through many tiles (the multi-tile paths
+    # that full-size calls take)
+    assert _lib.tsg_set_grid_limit(3) == 0
+    try:
+        assert np.array_equal(host(api.tsmttsm(dev(Ai), dev(Bi))), Ci)
+        assert np.array_equal(host(api.tsmm(dev(Ai), dev(Xi))), Pi)
+        assert np.array_equal(update(), Ui)
+    finally:
+        _lib.tsg_set_grid_limit(0)
 
 
 # (17, 17), (18, 18), (49, 49): the TSMM reads A as one contiguous run per wave

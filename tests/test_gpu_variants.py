@@ -81,6 +81,14 @@ def test_every_candidate_matches_oracle(tlib, op, cplx, M, N):
             gotf = run(tlib, op, cplx, dAf, dBf)
             if not np.all(np.abs(gotf - reff) <= 1e-12 * bound):
                 bad.append(name + " (float)")
+            # three blocks: every block works through many tiles of the short
+            # matrix (register rings, reuse of staged data), as at full size
+            assert tlib.tsg_set_grid_limit(3) == 0
+            try:
+                if not np.array_equal(run(tlib, op, cplx, dA, dB), ref):
+                    bad.append(name + " (integer, 3 blocks)")
+            finally:
+                tlib.tsg_set_grid_limit(0)
     finally:
         tlib.tsg_force_variant(None)
     assert not bad, bad
