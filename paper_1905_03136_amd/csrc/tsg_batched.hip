@@ -318,6 +318,180 @@ __device__ __attribute__((noinline)) void slab_update(const Item* items, const D
     tsg::pipeline<NBUF>((int64_t)wave, nsteps, (int64_t)kWPB, fr, load, compute);
 }
 
+// ------------------------------------------- slab reads (contiguous rows)
+// With ldv = M and ldw = N the rows one wave takes in one step are one
+// contiguous run of V and one of W.  Each run is read through a buffer
+// resource that ends where the run (or the slab) ends, so loads past it
+// return zero and cost no memory traffic: the wave issues consecutive 8-byte
+// loads (512 contiguous bytes per instruction, whatever the widths), stages
+// the runs in its own LDS region and reads the matrix-core operands back from
+// there.  Phase 2 writes its results back into the staged W run and stores
+// the run with consecutive 8-byte stores.  The lanes read each other's staged
+// values: one wave's LDS accesses complete in order, and a compiler memory
+// barrier on each side of the staging keeps the compiler from treating them
+// as independent.
+constexpr int kRunMax = 1280;  // doubles of staged runs per wave (largest path: 16 rows x (64 + 16))
+__shared__ double g_run[kWPB * kRunMax];
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t run_rsrc(const double* base, int n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, n * 8, kRsrcWord3);
+}
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("" ::: "memory"); }
+
+// Phase 1 on runs: steps of 4U rows; lane (r, c) takes V(k0 + r, 16 mb + c)
+// and W(k0 + r, c) of each group of four rows from the staged runs (columns
+// past M or N read the next row's values, which reach only outputs that are
+// never stored).
+template <int MB, int U, int NBUF>
+__device__ __attribute__((noinline)) void run_partial(const Item* items, const DevDesc* descs, int q, double* parts_)
+{
+    Item it;
+    DevDesc d;
+    fetch_item(items, descs, q, it, d);
+    double* __restrict__ parts = uni(parts_);
+    double* lds = g_lds;
+    int lane = threadIdx.x & (kWave - 1);
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    __asm__ volatile("" : "+v"(lane), "+s"(wave));
+    const int lr = lane >> 4, lc = lane & 15;
+    const int M = d.M, N = d.N;
+    constexpr int NLV = U * MB, NLW = U;  // loads per lane: 4U rows x 16 MB (or 16) columns at most
+    static_assert(kWave * (NLV + NLW) <= kRunMax, "staged runs exceed the wave's LDS region");
+    double* run = g_run + wave * kRunMax;
+    double* runw = run + kWave * NLV;
+    dbl4 acc[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+    struct Frag {
+        double v[NLV];
+        double w[NLW];
+    };
+    Frag fr[NBUF];
+    auto load = [&](int64_t g, Frag& f) {
+        const int64_t r0 = it.row0 + (int64_t)4 * U * g;
+        const int rows = (int)min((int64_t)4 * U, (int64_t)it.nrows - 4 * U * g);
+        const auto rv = run_rsrc(d.V + r0 * M, rows * M);
+        const auto rw = run_rsrc(d.W + r0 * N, rows * N);
+#pragma unroll
+        for (int i = 0; i < NLV; ++i) f.v[i] = ld_buf<kNT>(rv, (i * kWave + lane) * 8);
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) f.w[i] = ld_buf<kNT>(rw, (i * kWave + lane) * 8);
+    };
+    auto compute = [&](int64_t, Frag& f) {
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < NLV; ++i) run[i * kWave + lane] = f.v[i];
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) runw[i * kWave + lane] = f.w[i];
+        lds_barrier();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double b = runw[(4 * u + lr) * N + lc];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) acc[i] = mfma16(run[(4 * u + lr) * M + 16 * i + lc], b, acc[i]);
+        }
+    };
+    const int64_t nsteps = (it.nrows + 4 * U - 1) / (4 * U);
+    tsg::pipeline<NBUF>((int64_t)wave, nsteps, (int64_t)kWPB, fr, load, compute);
+
+    for (int w = 0; w < kWPB; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 16 * i + lr + 4 * r;
+                    if (m < M && lc < N) {
+                        const int e = m * N + lc;
+                        lds[e] = (w == 0) ? acc[i][r] : lds[e] + acc[i][r];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    double* part = parts + it.slot_off;
+    for (int e = threadIdx.x; e < M * N; e += kThreads) part[e] = lds[e];
+}
+
+// Phase 2 on runs: steps of 16U rows.  Lane (r, c) takes V(16 b + c, 4 s + r)
+// from the staged V run (zeroed past M: the value there belongs to the next
+// row, and although the staged C is zero there, a non-finite value times zero
+// is not zero) and starts its accumulator from the staged old
+// W(16 b + r + 4 q, c); the results go back to the same W positions (lanes
+// with c < N only: a column past N addresses the next row) and the W run is
+// stored.
+template <int MS, int U, int NBUF>
+__device__ __attribute__((noinline)) void run_update(const Item* items, const DevDesc* descs, int q)
+{
+    Item it;
+    DevDesc d;
+    fetch_item(items, descs, q, it, d);
+    const double* cf = g_lds;
+    int lane = threadIdx.x & (kWave - 1);
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    __asm__ volatile("" : "+v"(lane), "+s"(wave));
+    const int lr = lane >> 4, lc = lane & 15;
+    const int M = d.M, N = d.N;
+    constexpr int NLV = U * MS, NLW = 4 * U;  // 16U rows x 4 MS (or 16) columns at most
+    static_assert(kWave * (NLV + NLW) <= kRunMax, "staged runs exceed the wave's LDS region");
+    double* run = g_run + wave * kRunMax;
+    double* runw = run + kWave * NLV;
+    const bool kok = 4 * (MS - 1) + lr < M;
+    const bool nok = lc < N;
+    struct Frag {
+        double v[NLV];
+        double w[NLW];
+    };
+    Frag fr[NBUF];
+    auto load = [&](int64_t g, Frag& f) {
+        const int64_t r0 = it.row0 + (int64_t)16 * U * g;
+        const int rows = (int)min((int64_t)16 * U, (int64_t)it.nrows - 16 * U * g);
+        const auto rv = run_rsrc(d.V + r0 * M, rows * M);
+        const auto rw = run_rsrc(d.W + r0 * N, rows * N);
+#pragma unroll
+        for (int i = 0; i < NLV; ++i) f.v[i] = ld_buf<kNT>(rv, (i * kWave + lane) * 8);
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) f.w[i] = ld_buf<kNT>(rw, (i * kWave + lane) * 8);
+    };
+    auto compute = [&](int64_t g, Frag& f) {
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < NLV; ++i) run[i * kWave + lane] = f.v[i];
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) runw[i * kWave + lane] = f.w[i];
+        lds_barrier();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dbl4 acc;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) acc[qq] = runw[(16 * u + lr + 4 * qq) * N + lc];
+#pragma unroll
+            for (int s = 0; s < MS; ++s) {
+                double a = run[(16 * u + lc) * M + 4 * s + lr];
+                if (s == MS - 1) a = kok ? a : 0.0;
+                acc = mfma16(a, cf[s * kWave + lane], acc);
+                // operands are read four steps at a time (the products keep
+                // running meanwhile): all of them at once would not fit the
+                // register budget of the wide paths
+                if (s % 4 == 3) lds_barrier();
+            }
+            if (nok) {
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) runw[(16 * u + lr + 4 * qq) * N + lc] = acc[qq];
+            }
+        }
+        lds_barrier();
+        const int64_t r0 = it.row0 + (int64_t)16 * U * g;
+        const int rows = (int)min((int64_t)16 * U, (int64_t)it.nrows - 16 * U * g);
+        const auto rw = run_rsrc(d.W + r0 * N, rows * N);
+#pragma unroll
+        for (int i = 0; i < NLW; ++i) st_buf(rw, (i * kWave + lane) * 8, runw[i * kWave + lane]);
+    };
+    const int64_t nsteps = (it.nrows + 16 * U - 1) / (16 * U);
+    tsg::pipeline<NBUF>((int64_t)wave, nsteps, (int64_t)kWPB, fr, load, compute);
+}
+
 // Two waves per SIMD: every path fits in 256 registers without spilling.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ items, int total,
@@ -336,12 +510,22 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
         const Item it = items[q];
         const DevDesc d = descs[it.inst];
         if (it.phase == 1) {
-            // rows per step chosen so that a register set holds about 20 values
-            switch ((d.M + 15) / 16) {
-            case 1: slab_partial<1, 8, 2>(items, descs, q, parts); break;
-            case 2: slab_partial<2, 4, 2>(items, descs, q, parts); break;
-            case 3: slab_partial<3, 2, 2>(items, descs, q, parts); break;
-            default: slab_partial<4, 2, 2>(items, descs, q, parts); break;
+            // rows per step chosen so that a register set holds about 20 values;
+            // contiguous instances read their rows as runs
+            if (d.ldv == d.M && d.ldw == d.N) {
+                switch ((d.M + 15) / 16) {
+                case 1: run_partial<1, 8, 2>(items, descs, q, parts); break;
+                case 2: run_partial<2, 4, 2>(items, descs, q, parts); break;
+                case 3: run_partial<3, 2, 2>(items, descs, q, parts); break;
+                default: run_partial<4, 1, 2>(items, descs, q, parts); break;
+                }
+            } else {
+                switch ((d.M + 15) / 16) {
+                case 1: slab_partial<1, 8, 2>(items, descs, q, parts); break;
+                case 2: slab_partial<2, 4, 2>(items, descs, q, parts); break;
+                case 3: slab_partial<3, 2, 2>(items, descs, q, parts); break;
+                default: slab_partial<4, 2, 2>(items, descs, q, parts); break;
+                }
             }
             fence_release();  // this wave's part of the partial, before the arrival is counted
             __syncthreads();
@@ -381,7 +565,26 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
                 lds[idx] = (m < d.M && n < d.N) ? -d.C[(int64_t)m * d.ldc + n] : 0.0;
             }
             __syncthreads();
-            switch (MS) {
+            if (d.ldv == d.M && d.ldw == d.N) {
+                switch (MS) {
+                case 1: run_update<1, 2, 2>(items, descs, q); break;
+                case 2: run_update<2, 2, 2>(items, descs, q); break;
+                case 3: run_update<3, 2, 2>(items, descs, q); break;
+                case 4: run_update<4, 2, 2>(items, descs, q); break;
+                case 5: run_update<5, 1, 2>(items, descs, q); break;
+                case 6: run_update<6, 1, 2>(items, descs, q); break;
+                case 7: run_update<7, 1, 2>(items, descs, q); break;
+                case 8: run_update<8, 1, 2>(items, descs, q); break;
+                case 9: run_update<9, 1, 2>(items, descs, q); break;
+                case 10: run_update<10, 1, 2>(items, descs, q); break;
+                case 11: run_update<11, 1, 2>(items, descs, q); break;
+                case 12: run_update<12, 1, 2>(items, descs, q); break;
+                case 13: run_update<13, 1, 2>(items, descs, q); break;
+                case 14: run_update<14, 1, 2>(items, descs, q); break;
+                case 15: run_update<15, 1, 2>(items, descs, q); break;
+                default: run_update<16, 1, 2>(items, descs, q); break;
+                }
+            } else switch (MS) {
             case 1: slab_update<1, 4, 2>(items, descs, q); break;
             case 2: slab_update<2, 2, 2>(items, descs, q); break;
             case 3: slab_update<3, 2, 2>(items, descs, q); break;
