@@ -254,8 +254,12 @@ def generic_variants():
         for ms in (4, 8, 16):
             for nb in (1, 2, 4):
                 u = 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1
-                out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb,
-                                cfg=dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)))
+                # a twin reading the old B with A serves calls with beta != 0
+                for rb in (1, 0):
+                    cfg = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)
+                    if rb:
+                        cfg["RB"] = 1
+                    out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb, cfg=cfg))
     return out
 
 

@@ -1129,7 +1129,12 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 }
         }
         const bool full = (t + 1) * RT <= K;
-        constexpr bool kStream = stream_rows(NC * (int)sizeof(S));  // whole lines per row (see st_plain)
+        // streaming stores where rows are whole lines or whole lines hold whole
+        // rows; with several n-blocks per row, one store covers 16 elements of
+        // each of four rows, which must be whole lines too (binary32: 64 bytes,
+        // half a line, and the halves were written to memory separately: 26%
+        // extra write traffic at 64 x 64), else the cache merges them
+        constexpr bool kStream = stream_rows(NC * (int)sizeof(S)) && (NB == 1 || 16 * sizeof(S) >= 128);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t rbase = t * RT + (int64_t)(wave * U + u) * 16 + lr;

@@ -43,10 +43,12 @@ def check_instance(V, W0, C_gpu, W_gpu, what=""):
     check_bound(W_gpu, W_ref, np.abs(W0) + np.abs(V) @ np.abs(C_gpu), what=what + " W")
 
 
-# (K, M, N): the workload's widths, odd widths, a K smaller than a step, K = 1 and K = 0
+# (K, M, N): the workload's widths, odd widths, a K smaller than a step, K = 1 and K = 0,
+# and narrow widths whose first phase packs P = 16 / max(M, N) = 3, 2, 8, 5 rows per product
 SHAPES = [(100003, 64, 16), (70001, 32, 8), (50000, 16, 4), (65536, 8, 1), (30011, 4, 16),
           (20001, 13, 7), (9999, 17, 16), (12345, 63, 15), (777, 3, 5), (15, 64, 1), (1, 1, 1),
-          (0, 8, 4), (40000, 48, 12), (25000, 1, 16), (33333, 20, 3), (11111, 36, 11)]
+          (0, 8, 4), (40000, 48, 12), (25000, 1, 16), (33333, 20, 3), (11111, 36, 11),
+          (40009, 5, 3), (12007, 7, 2), (5003, 2, 1), (3001, 1, 3)]
 
 
 def _instances(shapes, seed, integer=False):
