@@ -11,6 +11,7 @@ min(HBM, FP64) roofline, the roofline record of the dominant kernel and the
 CPU oracle timed on a bounded sample of the same sweep.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --all-widths      # every square width 1..64 instead (one JSON line each)
 """
 import argparse
 import glob
@@ -232,6 +233,35 @@ def cpu_baseline(K_sample):
             "seconds": t_total, "cpu": platform.processor() or platform.machine()}
 
 
+def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3):
+    """Every square width M = N = 1..64, D and Z, both products at K rows:
+    median time of `reps` calls (one width at a time, exact-size operands)
+    and the fraction of the spec roofline; one JSON line per width, then a
+    summary line with the mean and the minimum fraction per (dtype, op)."""
+    rows = []
+    for cplx in (False, True):
+        for w in range(1, 65):
+            A = inputs.device_uniform(K, w, w, inputs.STREAM_A, cplx, dev)
+            B = inputs.device_uniform(K, w, w, inputs.STREAM_B, cplx, dev)
+            X = inputs.device_uniform(w, w, w, inputs.STREAM_C, cplx, dev)
+            Co = torch.empty((w, w), dtype=A.dtype, device=dev)
+            rec = {"dtype": "Z" if cplx else "D", "M": w, "N": w, "K": K}
+            for op, fn in (("tsmttsm", lambda: api.tsmttsm(A, B, out=Co)), ("tsmm", lambda: api.tsmm(A, X, out=B))):
+                t = time_call(torch, fn, reps=reps, warmup=1)
+                byts, flops = algorithmic(op, cplx, K, w, w)
+                rec[op] = {"us": round(t * 1e6, 1), "roof_frac": round(max(byts / HBM_PEAK, flops / FP64_PEAK) / t, 4),
+                           "kernel": api.kernel_name(op, A.dtype, w, w)}
+            print(json.dumps(rec), flush=True)
+            rows.append(rec)
+            del A, B, X, Co
+    summary = {}
+    for dt in ("D", "Z"):
+        for op in ("tsmttsm", "tsmm"):
+            f = [r[op]["roof_frac"] for r in rows if r["dtype"] == dt]
+            summary["%s_%s" % (dt, op)] = {"mean": round(sum(f) / len(f), 4), "min": min(f)}
+    print(json.dumps({"all_widths_summary": summary}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +273,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="rows of the oracle sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
+    ap.add_argument("--all-widths", action="store_true",
+                    help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "
@@ -254,6 +286,9 @@ def main():
     from paper_1905_03136_amd import api, inputs
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.all_widths:
+        all_widths(torch, api, inputs, dev)
+        return
     print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
     K = K_SWEEP
     # Every width has its own exact-size A (K x M) and B (K x N), as a caller's
