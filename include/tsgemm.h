@@ -182,7 +182,8 @@ typedef struct tsg_orth_plan_t *tsg_orth_plan;
  * (partial sums, counters, flags) and captures one launch into a hipGraph on
  * a private stream.  rows_per_item > 0 fixes the slab height of every
  * instance; <= 0 picks it per instance (about 4 MiB of input per slab, at
- * most 256 slabs per instance).  Instances are queued largest first.
+ * most 256 slabs per instance) and cuts the updates at the end of the queue
+ * into half and quarter slabs.  Instances are queued largest first.
  * Errors: TSG_E_ARG (null plan/descs, count < 1, K_i < 0, M_i or N_i < 1,
  * ld too small, null or misaligned pointer with K_i > 0, null C_i),
  * TSG_E_UNSUPPORTED (M_i > 64, N_i > 16, slab height > 2^30), TSG_E_NOMEM,

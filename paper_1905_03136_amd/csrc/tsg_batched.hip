@@ -816,38 +816,62 @@ tsg_status tsg_orth_plan_create(tsg_orth_plan* plan, int32_t count, const tsg_or
         part_total += nslab * (int64_t)s.M * s.N;
         dd[i] = d;
     }
+    int dev = 0, cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&orth_persistent),
+                                                         kThreads, 0);
+    if (e != hipSuccess || cus < 1) return fail(TSG_E_HIP, "no usable HIP device (%lld)", (long long)e);
+    const int64_t resident = (int64_t)cus * std::max(occ, 1);
     std::vector<Item> items;
-    for (int phase = 1; phase <= 2; ++phase)
-        for (int i : order) {
-            const DevDesc& d = dd[i];
-            if (phase == 2 && d.K == 0) continue;
-            for (int64_t j = 0; j < d.nparts; ++j) {
+    for (int i : order) {
+        const DevDesc& d = dd[i];
+        for (int64_t j = 0; j < d.nparts; ++j) {
+            Item it{};
+            it.row0 = j * rows[i];
+            it.nrows = (int32_t)std::min(rows[i], d.K - it.row0);
+            it.inst = i;
+            it.phase = 1;
+            it.slot_off = d.part0 + j * (int64_t)d.M * d.N;
+            items.push_back(it);
+        }
+    }
+    // Phase-2 items do not depend on one another, so with automatic sizing the
+    // end of the queue is cut finer: the last `resident` items cover a quarter
+    // of a slab each and the 2 * resident before them half a slab.  The blocks
+    // that run on alone after the queue has drained then hold short items.
+    // The queue is built back to front, then reversed.
+    std::vector<Item> upd;
+    for (auto o = order.rbegin(); o != order.rend(); ++o) {
+        const int i = *o;
+        const DevDesc& d = dd[i];
+        if (d.K == 0) continue;
+        for (int64_t j = d.nparts - 1; j >= 0; --j) {
+            const int64_t row0 = j * rows[i], nr = std::min(rows[i], d.K - row0);
+            const int64_t made = (int64_t)upd.size();
+            const int64_t f = rows_per_item > 0 ? 1 : made < resident ? 4 : made < 3 * resident ? 2 : 1;
+            const int64_t piece = f > 1 ? std::max<int64_t>(16, round16((nr + f - 1) / f)) : nr;
+            const int64_t np = (nr + piece - 1) / piece;
+            for (int64_t k = np - 1; k >= 0; --k) {
                 Item it{};
-                it.row0 = j * rows[i];
-                it.nrows = (int32_t)std::min(rows[i], d.K - it.row0);
+                it.row0 = row0 + k * piece;
+                it.nrows = (int32_t)std::min(piece, nr - k * piece);
                 it.inst = i;
-                it.phase = phase;
-                it.slot_off = phase == 1 ? d.part0 + j * (int64_t)d.M * d.N : 0;
-                items.push_back(it);
+                it.phase = 2;
+                upd.push_back(it);
             }
         }
+    }
+    items.insert(items.end(), upd.rbegin(), upd.rend());
     if (items.size() > ((size_t)1 << 30)) return fail(TSG_E_UNSUPPORTED, "too many work items");
 
     tsg_orth_plan p = new (std::nothrow) tsg_orth_plan_t();
     if (!p) return fail(TSG_E_NOMEM, "host allocation failed");
     p->count = count;
     p->total = (int)items.size();
-    int cus = 0, occ = 0;
-    hipError_t e = hipGetDevice(&p->dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&orth_persistent),
-                                                         kThreads, 0);
-    if (e != hipSuccess || cus < 1) {
-        delete p;
-        return fail(TSG_E_HIP, "no usable HIP device (%lld)", (long long)e);
-    }
-    p->grid = std::max(1, std::min(cus * std::max(occ, 1), p->total));
+    p->dev = dev;
+    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident, p->total));
     const Ctrl ctrl0{0u, 0u, 0u, kDefaultSpin};
     if (hipMalloc(&p->d_descs, sizeof(DevDesc) * count) != hipSuccess ||
         hipMalloc(&p->d_items, sizeof(Item) * items.size()) != hipSuccess ||
