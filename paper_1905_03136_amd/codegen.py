@@ -177,7 +177,10 @@ def _candidates(op, dt, M, N):
             for w in (4, 8):
                 for nbuf in (2, 4):
                     out.append(dict(kind="packed", U=u, WPB=w, NBUF=nbuf))
-    if M >= 4 or N >= 16:
+    # matrix cores from three columns of A up (one 4-deep slice with a zero
+    # fourth column already beats row packing at 3 x 3; at 1 and 2 the
+    # vector and packed kernels stay ahead)
+    if M >= 3 or N >= 16:
         ms, nb = _ceil(M, 4), _ceil(N, 16)
         for u in (1, 2, 4):
             for w in (4, 8):
@@ -247,19 +250,24 @@ def generic_variants():
             u = max(1, min(4, 8 // ((mb + nb) * cw)))
             out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
                             cfg=dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)))
-        # TSMM
-        for mx in (() if is_f32(dt) else (4, 8) if not cplx else (4,)):
-            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=mx,
-                            cfg=dict(kind="valu", MX=mx, NX=mx, U=2, VA=0, VB=0, WPB=WPB)))
-        for ms in (4, 8, 16):
-            for nb in (1, 2, 4):
-                u = 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1
-                # a twin reading the old B with A serves calls with beta != 0
-                for rb in (1, 0):
-                    cfg = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)
-                    if rb:
-                        cfg["RB"] = 1
-                    out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb, cfg=cfg))
+        # TSMM: the vector kernel only up to 2 x 2 (with run-time widths it
+        # keeps C in registers sized for the maximum and falls far behind the
+        # matrix cores beyond that: 0.3-1 TB/s at 1 x 8, 3 x 8, 1 x 4), then
+        # matrix-core kernels whose contraction depth follows M in 4-wide
+        # slices (one or two slices for M <= 8: 4.4-5.3 TB/s at 3 x 8, 1 x 8,
+        # 8 x 3, where four slices reached 3-4 TB/s)
+        if not is_f32(dt):
+            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=2, maxN=2,
+                            cfg=dict(kind="valu", MX=2, NX=2, U=2, VA=0, VB=0, WPB=WPB)))
+        shallow = [(1, 1, 4 if not cplx else 2, 8), (2, 1, 2, 8)]
+        deep = [(ms, nb, 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1, WPB) for ms in (4, 8, 16) for nb in (1, 2, 4)]
+        for ms, nb, u, w in shallow + deep:
+            # a twin reading the old B with A serves calls with beta != 0
+            for rb in (1, 0):
+                cfg = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)
+                if rb:
+                    cfg["RB"] = 1
+                out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb, cfg=cfg))
     return out
 
 
