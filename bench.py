@@ -267,10 +267,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    # 2^23 rows: the 36 calls of the sweep move 134 GB at that K, about 11 s of
-    # oracle work on 16 host threads (12.5 GB/s measured at 2^21 rows); inputs
-    # of at most 8.6 GB per matrix
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="rows of the oracle sample (0 = skip)")
+    # 3 * 2^22 rows: the 36 calls of the sweep move 201 GB at that K, about 13 s
+    # of oracle work on 16 host threads (15.4 GB/s measured at 2^23 rows);
+    # inputs of at most 12.9 GB per matrix
+    ap.add_argument("--cpu-sample", type=int, default=3 << 22, help="rows of the oracle sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
     ap.add_argument("--all-widths", action="store_true",
