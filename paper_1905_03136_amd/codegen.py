@@ -234,22 +234,55 @@ def default_config(op, dt, M, N):
     return dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=WPB)
 
 
+# Run-time-width configurations chosen by a probe of non-square pairs at
+# K = 2^24 (forced variants, median of three calls):
+#   TSMTTSM block grid (m blocks, n blocks) -> (MB, NB, MW, U, WPB), real / complex.
+#   The 2 x 3, 3 x 2 and 3 x 3 grids halve the time of pairs such as 17 x 33
+#   (D 2.88 -> 1.35 ms, Z 7.7 -> 3.7 ms) that the 2 x 4 / 4 x 2 grids padded;
+#   two rows in flight and eight waves took 30 x 60 from 3.16 to 2.05 ms (D).
+_GEN_TSMTTSM = {
+    (1, 2): ((1, 2, 1, 2, 4), (1, 2, 1, 1, 4)),
+    (2, 1): ((2, 1, 1, 2, 4), (2, 1, 1, 1, 4)),
+    (2, 2): ((2, 2, 1, 2, 8), (2, 2, 1, 2, 8)),
+    (1, 4): ((1, 4, 1, 1, 4), (1, 4, 1, 1, 4)),
+    (4, 1): ((4, 1, 1, 1, 4), (4, 1, 1, 1, 4)),
+    (2, 3): ((2, 3, 1, 2, 8), (1, 3, 2, 2, 8)),
+    (3, 2): ((3, 2, 1, 2, 8), (3, 2, 1, 2, 4)),
+    (3, 3): ((3, 3, 1, 2, 8), (1, 3, 3, 1, 12)),
+    (2, 4): ((2, 4, 1, 2, 8), (2, 4, 1, 1, 4)),
+    (4, 2): ((4, 2, 1, 2, 8), (2, 2, 2, 2, 8)),
+    (4, 4): ((2, 4, 2, 1, 4), (1, 4, 4, 1, 4)),
+}
+#   TSMM contraction depth in 4-wide slices and n blocks -> (U, WPB).
+#   Depths of 6 and 12 slices (M <= 24, M <= 48) run 17 x 9 in 1.17 instead
+#   of 1.40 ms and 40 x 8 in 2.19 instead of 2.79 ms (D).
+
+
+def _gen_tsmm_cfg(ms, nb, cplx):
+    if ms <= 2:
+        return (2 if cplx or ms == 2 else 4), 8
+    if ms in (6, 12):
+        if not cplx:
+            return 2, 8
+        return (2 if ms == 6 and nb == 1 else 1), (4 if ms == 12 and nb == 4 else 8)
+    cw = 2 if cplx else 1
+    return (2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1), WPB
+
+
 def generic_variants():
-    """Run-time-width variants: every (M, N) in [1, 64]^2 is served by one."""
+    """Run-time-width variants: every (M, N) in [1, 64]^2 is served by one.
+    The runtime takes the first one that covers (M, N), so each list runs
+    from the smallest covering shape to the largest."""
     out = []
     for dt, (_, cplx) in DTYPES.items():
         cw = 2 if cplx else 1
         # TSMTTSM: row packing up to 16, then blocked matrix-core kernels
         out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16, maxN=16,
                         cfg=dict(kind="packed", U=4, WPB=WPB)))
-        for mbt, nb in ((1, 2), (2, 1), (2, 2), (1, 4), (4, 1), (2, 4), (4, 2), (4, 4)):
-            mw = 1
-            while mbt * nb * 4 * cw > 32 * mw and mw < mbt:
-                mw *= 2
-            mb = _ceil(mbt, mw)
-            u = max(1, min(4, 8 // ((mb + nb) * cw)))
+        for (mbt, nb), cfgs in _GEN_TSMTTSM.items():
+            mb, nbb, mw, u, w = cfgs[1 if cplx else 0]
             out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
-                            cfg=dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=WPB)))
+                            cfg=dict(kind="mfma", MB=mb, NB=nbb, MW=mw, U=u, WPB=w)))
         # TSMM: the vector kernel only up to 2 x 2 (with run-time widths it
         # keeps C in registers sized for the maximum and falls far behind the
         # matrix cores beyond that: 0.3-1 TB/s at 1 x 8, 3 x 8, 1 x 4), then
@@ -259,14 +292,17 @@ def generic_variants():
         if not is_f32(dt):
             out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=2, maxN=2,
                             cfg=dict(kind="valu", MX=2, NX=2, U=2, VA=0, VB=0, WPB=WPB)))
-        shallow = [(1, 1, 4 if not cplx else 2, 8), (2, 1, 2, 8)]
-        deep = [(ms, nb, 2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1, WPB) for ms in (4, 8, 16) for nb in (1, 2, 4)]
-        for ms, nb, u, w in shallow + deep:
-            # a twin reading the old B with A serves calls with beta != 0
+        shapes = [(1, 1), (2, 1)] + [(ms, nb) for ms in (4, 6, 8, 12, 16) for nb in (1, 2, 4)]
+        for ms, nb in shapes:
+            u, w = _gen_tsmm_cfg(ms, nb, cplx)
+            # a twin reading the old B with A serves calls with beta != 0 (its
+            # register ring of B does not fit eight-wave blocks from 6 slices)
             for rb in (1, 0):
                 cfg = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)
                 if rb:
                     cfg["RB"] = 1
+                    if ms >= 6:
+                        cfg["WPB"] = WPB
                 out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb, cfg=cfg))
     return out
 
