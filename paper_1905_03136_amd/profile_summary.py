@@ -110,7 +110,7 @@ def summarise(trace, fetch, write, bench_json, command, probe_bytes):
     return rows, f_scale, w_scale, bench, roof
 
 
-def render(rows, f_scale, w_scale, bench, roof, commands, title):
+def render(rows, f_scale, w_scale, bench, roof, commands, title, dominant=True):
     lines = ["# %s" % title, "", "Commands (run from the repository root on one MI355X):", ""]
     lines += ["    " + c for c in commands]
     lines += ["", "Counter scale factors from the stream probes of known size: FETCH_SIZE x %.3f, "
@@ -125,7 +125,10 @@ def render(rows, f_scale, w_scale, bench, roof, commands, title):
             "%.1f" % (r["read"] / 1e6) if r["read"] is not None else "-",
             "%.1f" % (r["written"] / 1e6) if r["written"] is not None else "-"))
     rec = None
-    kern = roof.get("kernel_symbol")
+    kern = roof.get("kernel_symbol") if dominant else None
+    if not dominant:
+        lines += ["", "No per-launch record of the bench's dominant kernel here: this run launches some kernels "
+                  "at more than one size, and the per-launch figures above average over them."]
     if kern:
         hit = [r for r in rows if r["full"].startswith(kern + "(")]
         if hit and hit[0]["read"] is not None and hit[0]["written"] is not None:
@@ -172,10 +175,12 @@ def main(argv=None):
     ap.add_argument("--probe-bytes", type=float, default=float(8 << 30))
     ap.add_argument("--title", default="Kernel profile")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--no-dominant", action="store_true",
+                    help="omit the dominant kernel's per-launch record (runs that launch a kernel at several sizes)")
     a = ap.parse_args(argv)
     rows, fs, ws, bench, roof = summarise(a.trace, a.fetch, a.write, a.bench_json, a.command, a.probe_bytes)
     with open(a.out, "w") as f:
-        f.write(render(rows, fs, ws, bench, roof, a.command, a.title))
+        f.write(render(rows, fs, ws, bench, roof, a.command, a.title, dominant=not a.no_dominant))
     print("wrote %s" % a.out)
 
 
