@@ -12,6 +12,7 @@ CPU oracle timed on a bounded sample of the same sweep.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --all-widths      # every square width 1..64 instead (one JSON line each)
+    python bench.py --all-widths --vendor   # ... with torch.matmul (rocBLAS / hipBLASLt) beside each
 """
 import argparse
 import json
@@ -232,11 +233,15 @@ def cpu_baseline(K_sample):
             "seconds": t_total, "cpu": platform.processor() or platform.machine()}
 
 
-def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3):
+def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False):
     """Every square width M = N = 1..64, D and Z, both products at K rows:
     median time of `reps` calls (one width at a time, exact-size operands)
     and the fraction of the spec roofline; one JSON line per width, then a
-    summary line with the mean and the minimum fraction per (dtype, op)."""
+    summary line with the mean and the minimum fraction per (dtype, op).
+    With `vendor`, the same products through torch.matmul (rocBLAS /
+    hipBLASLt GEMMs: A^T B as a transposed view times B, A C) are timed on
+    the same operands beside ours -- the vendor-library context of the
+    paper's library comparison (Section 1.5), measured on this GPU."""
     rows = []
     for cplx in (False, True):
         for w in range(1, 65):
@@ -248,8 +253,15 @@ def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3):
             for op, fn in (("tsmttsm", lambda: api.tsmttsm(A, B, out=Co)), ("tsmm", lambda: api.tsmm(A, X, out=B))):
                 t = time_call(torch, fn, reps=reps, warmup=1)
                 byts, flops = algorithmic(op, cplx, K, w, w)
-                rec[op] = {"us": round(t * 1e6, 1), "roof_frac": round(max(byts / HBM_PEAK, flops / FP64_PEAK) / t, 4),
+                roof = max(byts / HBM_PEAK, flops / FP64_PEAK)
+                rec[op] = {"us": round(t * 1e6, 1), "roof_frac": round(roof / t, 4),
                            "kernel": api.kernel_name(op, A.dtype, w, w)}
+                if vendor:
+                    vfn = (lambda: torch.matmul(A.t(), B, out=Co)) if op == "tsmttsm" else \
+                        (lambda: torch.matmul(A, X, out=B))
+                    tv = time_call(torch, vfn, reps=reps, warmup=1)
+                    rec[op].update(vendor_us=round(tv * 1e6, 1), vendor_roof_frac=round(roof / tv, 4),
+                                   speedup_vs_vendor=round(tv / t, 3))
             print(json.dumps(rec), flush=True)
             rows.append(rec)
             del A, B, X, Co
@@ -258,6 +270,12 @@ def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3):
         for op in ("tsmttsm", "tsmm"):
             f = [r[op]["roof_frac"] for r in rows if r["dtype"] == dt]
             summary["%s_%s" % (dt, op)] = {"mean": round(sum(f) / len(f), 4), "min": min(f)}
+            if vendor:
+                v = [r[op]["vendor_roof_frac"] for r in rows if r["dtype"] == dt]
+                sp = [r[op]["speedup_vs_vendor"] for r in rows if r["dtype"] == dt]
+                summary["%s_%s" % (dt, op)].update(
+                    vendor_mean=round(sum(v) / len(v), 4), vendor_min=min(v), vendor_max=max(v),
+                    speedup_min=min(sp), speedup_median=sorted(sp)[len(sp) // 2])
     print(json.dumps({"all_widths_summary": summary}), flush=True)
 
 
@@ -274,6 +292,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
     ap.add_argument("--all-widths", action="store_true",
                     help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
+    ap.add_argument("--vendor", action="store_true",
+                    help="with --all-widths: also time torch.matmul (rocBLAS / hipBLASLt) on the same operands")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "
@@ -286,7 +306,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if a.all_widths:
-        all_widths(torch, api, inputs, dev)
+        all_widths(torch, api, inputs, dev, vendor=a.vendor)
         return
     print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
     K = K_SWEEP
