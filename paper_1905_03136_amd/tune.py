@@ -226,6 +226,64 @@ def write_table(db_path, out_path, merge=None):
     print("[tune] wrote %s (%d entries)" % (out_path, len(entries)), flush=True)
 
 
+# design dimensions of a configuration, as the ablation reports them
+_DIMENSIONS = {
+    "mapping": lambda c: c["kind"],
+    "rows in flight U": lambda c: c.get("U"),
+    "ring depth NBUF": lambda c: c.get("NBUF", 2),
+    "waves per block": lambda c: c.get("WPB"),
+    "slab reads FL": lambda c: c.get("FL", 0),
+    "vector tails TL": lambda c: c.get("TL", 0),
+    "three-product form G3": lambda c: c.get("G3", 0),
+}
+
+
+def ablation(db_paths, ops=None):
+    """Cost of fixing one design dimension, from autotuner databases: for each
+    (op, dtype, M, N) and each value v of a dimension, the fastest correct
+    configuration with that value, as a slowdown over the fastest overall;
+    reported as the geometric mean and the maximum over the widths where v
+    was timed.  Later databases override earlier records of the same name."""
+    recs = {}
+    for path in db_paths:
+        with open(path) as f:
+            for line in f:
+                try:
+                    r = json.loads(line)
+                except ValueError:
+                    continue
+                if r.get("ok") and r.get("us") and r.get("M") and (not ops or r["op"] in ops):
+                    recs[(r["op"], r["dt"], r["M"], r["N"], r["name"])] = r
+    groups = {}
+    for (op, dt, M, N, _), r in recs.items():
+        groups.setdefault((op, dt, M, N), []).append(r)
+    out = {}
+    for (op, dt, M, N), rs in groups.items():
+        best = min(r["us"] for r in rs)
+        for dim, get in _DIMENSIONS.items():
+            by = {}
+            for r in rs:
+                v = get(r["cfg"])
+                by[v] = min(by.get(v, float("inf")), r["us"])
+            if len(by) < 2:
+                continue
+            for v, t in by.items():
+                out.setdefault((op, dt[0] if dt in ("r64", "r32") else "z", dim, v), []).append(t / best)
+    rows = []
+    for (op, kind, dim, v), xs in sorted(out.items(), key=lambda kv: [str(x) for x in kv[0]]):
+        gm = math.exp(sum(math.log(x) for x in xs) / len(xs))
+        rows.append((op, kind, dim, v, len(xs), gm, max(xs)))
+    return rows
+
+
+def cmd_ablate(args):
+    rows = ablation(args.db, set(args.ops.split(",")) if args.ops else None)
+    print("| op | real/complex | dimension | value | widths | slowdown (geo. mean) | slowdown (max) |")
+    print("|---|---|---|---|---:|---:|---:|")
+    for op, kind, dim, v, n, gm, mx in rows:
+        print("| %s | %s | %s | %s | %d | %.3f | %.2f |" % (op, "real" if kind == "r" else "complex", dim, v, n, gm, mx))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -243,6 +301,9 @@ def main(argv=None):
     r.add_argument("--reps", type=int, default=5)
     r.add_argument("--warmup", type=int, default=2)
     r.add_argument("--merge", default="", help="keep the entries of this table the run does not cover")
+    ab = sub.add_parser("ablate", help="cost of fixing each design dimension, from tuning databases")
+    ab.add_argument("--db", action="append", required=True, help="a tuning database (repeatable; later ones win)")
+    ab.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
     t = sub.add_parser("table")
     t.add_argument("--db", default="gpurun_out/tune_db.jsonl")
     t.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
@@ -252,6 +313,8 @@ def main(argv=None):
         cmd_build(a)
     elif a.cmd == "run":
         cmd_run(a)
+    elif a.cmd == "ablate":
+        cmd_ablate(a)
     else:
         write_table(a.db, a.out, a.merge)
 
