@@ -108,6 +108,29 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
                        void *C, int64_t ldc, void *stream);
 
 /*
+ * TSMTTSM that allocates nothing, for callers that cannot call hipMalloc:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same operation, arguments, validation and kernels as
+ * tsg_tsmttsm (so the same bits), but the per-block partial sums go to a
+ * fixed scratch array of 32 MiB that the library holds on each device for
+ * the life of the process, instead of the per-stream workspace.
+ *  - Its device address is resolved once per device, by tsg_init(device) or
+ *    by the first call on that device; neither allocates.
+ *  - A call whose partial sums would exceed the 32 MiB returns
+ *    TSG_E_UNSUPPORTED and enqueues nothing.  (Every shape of the supported
+ *    range needs at most 2048 blocks x M N (x2 complex) doubles on a grid
+ *    sized by occupancy; the largest, complex 64 x 64, 16 to 32 MiB.)
+ *  - Every call on one device shares that device's scratch and leaves its
+ *    partial sums there: calls that overlap in time on one device (different
+ *    streams, or host threads) race and give wrong results.  Order them on
+ *    one stream, or use tsg_tsmttsm.  Nothing in the scratch needs to start
+ *    at zero (each block writes its whole slot before the fold reads it).
+ */
+tsg_status tsg_tsmttsm_noalloc(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
+                               const void *A, int64_t lda, const void *B, int64_t ldb,
+                               void *C, int64_t ldc, void *stream);
+
+/*
  * TSMM (Section 4):
  *   B(k, n) = alpha * sum_{m=0}^{M-1} opA(A(k, m)) * C[m * ldc + n] + beta * B(k, n)
  * opA conjugates A when conjA != 0 (complex types only).  alpha and beta are

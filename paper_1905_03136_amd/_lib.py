@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "TSG_OK", 1: "TSG_E_ARG", 2: "TSG_E_UNSUPPORTED", 3: "TSG_E_N
 _i32, _i64, _vp, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
 PROTOTYPES = {
     "tsg_tsmttsm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "tsg_tsmttsm_noalloc": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "tsg_tsmm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
     "tsg_tsmm_op": (_i32, [_i32, _i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
     "tsg_orth_plan_create": (_i32, [_vp, _i32, _vp, _i64, _vp]),
@@ -86,6 +87,10 @@ def check(status):
 
 def tsg_tsmttsm(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream):
     return lib().tsg_tsmttsm(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream)
+
+
+def tsg_tsmttsm_noalloc(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream):
+    return lib().tsg_tsmttsm_noalloc(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream)
 
 
 def tsg_tsmm(dt, conjA, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream):

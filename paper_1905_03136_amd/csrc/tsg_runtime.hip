@@ -58,6 +58,14 @@ fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double
     }
 }
 
+// Fixed scratch of tsg_tsmttsm_noalloc: the per-block partial sums of one
+// launch (a slot of M N (x2 complex) doubles per block).  Every device the
+// library runs on holds its own copy for the life of the process.  In host
+// code the array's name is only a stand-in; kernels and copies take the
+// device address obtained once per device with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
 }  // namespace tsg
 
 namespace {
@@ -106,6 +114,7 @@ std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 std::map<std::pair<int, const tsg::Variant*>, int> g_occ;  // (device, variant) -> blocks per CU
+std::map<int, double*> g_scratch;  // device -> device address of its no-alloc scratch
 
 int is_complex(tsg_dtype dt) { return dt == TSG_C128 || dt == TSG_C64; }
 size_t elem_bytes(tsg_dtype dt)
@@ -157,6 +166,25 @@ int occupancy(int dev, const tsg::Variant& v)
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Device address of `dev`'s scratch array; `dev` must be the current device.
+// Resolved on the first use per device (tsg_init or the first no-alloc call).
+tsg_status scratch_of(int dev, double** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return TSG_OK;
+    }
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(tsg::scratch));
+    if (e != hipSuccess || !p)
+        return fail(TSG_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(p);
+    *out = static_cast<double*>(p);
+    return TSG_OK;
+}
 
 // Choose the variant: the exact (op, dtype, M, N) one if its access
 // requirements hold, else the first run-time-width variant covering (M, N).
@@ -291,12 +319,10 @@ hipError_t launch_fold(const tsg::Launch& p, bool cplx)
     return hipGetLastError();
 }
 
-}  // namespace
-
-extern "C" {
-
-tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, void* C, int64_t ldc, void* stream)
+// TSMTTSM launch shared by tsg_tsmttsm (per-stream workspace, allocated on
+// first need) and tsg_tsmttsm_noalloc (the device's fixed scratch array).
+tsg_status tsmttsm_call(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
+                        const void* B, int64_t ldb, void* C, int64_t ldc, void* stream, bool noalloc)
 {
     g_err.clear();
     if (op != TSG_OP_T && op != TSG_OP_C) return fail(TSG_E_ARG, "unknown op %d", (int)op);
@@ -322,16 +348,39 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
     p.ldx = ldb;
     p.Y = C;
     p.ldy = ldc;
-    Workspace* w = nullptr;
-    if ((s = get_workspace(dev, p.stream, tsmttsm_ws_bytes(p.grid, M, N, is_complex(dt)), &w)) != TSG_OK)
-        return s;
-    p.ws = static_cast<double*>(w->data);
+    const size_t need = tsmttsm_ws_bytes(p.grid, M, N, is_complex(dt));
+    if (noalloc) {
+        if (need > tsg::kScratchBytes)
+            return fail(TSG_E_UNSUPPORTED, "TSMTTSM %dx%d on %d blocks needs %zu bytes of partial sums, more than "
+                        "the %zu bytes of the no-alloc scratch", M, N, p.grid, need, tsg::kScratchBytes);
+        if ((s = scratch_of(dev, &p.ws)) != TSG_OK) return s;
+    } else {
+        Workspace* w = nullptr;
+        if ((s = get_workspace(dev, p.stream, need, &w)) != TSG_OK) return s;
+        p.ws = static_cast<double*>(w->data);
+    }
     v->launch(p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
     if (p.grid > 1 && (e = launch_fold(p, is_complex(dt))) != hipSuccess)
         return fail(TSG_E_HIP, "launch of the partial fold: %s", hipGetErrorString(e));
     return TSG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, void* stream)
+{
+    return tsmttsm_call(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream, false);
+}
+
+tsg_status tsg_tsmttsm_noalloc(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N, const void* A,
+                               int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* stream)
+{
+    return tsmttsm_call(dt, op, K, M, N, A, lda, B, ldb, C, ldc, stream, true);
 }
 
 tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32_t M, int32_t N, const void* A,
@@ -424,7 +473,17 @@ tsg_status tsg_init(int32_t device)
     if (e != hipSuccess || n == 0) return fail(TSG_E_HIP, "no HIP device: %s", hipGetErrorString(e));
     if (device < 0 || device >= n) return fail(TSG_E_ARG, "device %d out of range [0, %d)", device, n);
     DeviceInfo di;
-    return device_info(device, &di);
+    tsg_status s = device_info(device, &di);
+    if (s != TSG_OK) return s;
+    // the no-alloc scratch address of `device`, resolved with it current
+    int cur = -1;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return fail(TSG_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess)
+        return fail(TSG_E_HIP, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+    double* ws = nullptr;
+    s = scratch_of(device, &ws);
+    if (cur != device) hipSetDevice(cur);
+    return s;
 }
 
 void tsg_finalize(void)
