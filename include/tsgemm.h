@@ -46,16 +46,22 @@
 extern "C" {
 #endif
 
-/* Storage type of the tall matrices A and B.
+/* Storage type of the tall matrices A and B, and the arithmetic.
  * TSG_R64 / TSG_C128 are the paper's D and Z types (Section 1.1).
- * TSG_R32 / TSG_C64 are the precision form: A and B are stored in binary32
- * (halving the HBM traffic) while the small matrix C stays binary64 /
- * complex128; see tsg_tsmttsm and tsg_tsmm for the arithmetic. */
+ * The other four are the precision form: A and B are stored in binary32
+ * (real, or complex as two binary32; half the HBM traffic) while the small
+ * matrix C stays binary64 / complex128.  TSG_R32 / TSG_C64 compute in
+ * binary64 on the exactly widened values; TSG_R32_ACC32 / TSG_C64_ACC32
+ * form the products in binary32 and sum them in binary32 over stretches of
+ * at most 32 rows, all further sums (over stretches, threads, blocks) in
+ * binary64 -- see tsg_tsmttsm and tsg_tsmm for the error of each. */
 typedef enum {
     TSG_R64 = 0,
     TSG_C128 = 1,
     TSG_R32 = 2,
-    TSG_C64 = 3
+    TSG_C64 = 3,
+    TSG_R32_ACC32 = 4,
+    TSG_C64_ACC32 = 5
 } tsg_dtype;
 
 /* op(A) of TSMTTSM: the transpose, or for complex types the conjugate
@@ -83,8 +89,8 @@ typedef enum {
  *   C[m * ldc + n] = sum_{k=0}^{K-1} op(A(k, m)) * B(k, n),   0 <= m < M, 0 <= n < N
  * C is overwritten (never read).  K = 0 writes zeros.
  *
- * dt       storage type of A and B.  C is double (TSG_R64, TSG_R32) or
- *          interleaved complex double (TSG_C128, TSG_C64).
+ * dt       storage type of A and B.  C is double (real types) or
+ *          interleaved complex double (complex types).
  * op       TSG_OP_T or TSG_OP_C (conjugates A; complex types only).
  * K        rows of A and B, K >= 0 (64-bit; any size that fits in memory).
  * M, N     columns of A and B, 1 <= M, N <= 64 (else TSG_E_UNSUPPORTED).
@@ -92,8 +98,9 @@ typedef enum {
  * B, ldb   device pointer and leading dimension, ldb >= N.
  * C, ldc   device pointer and leading dimension, ldc >= N.
  * Pointers must be aligned to the storage element size (8 B for TSG_R64,
- * 16 B for TSG_C128, 4 B for TSG_R32, 8 B for TSG_C64) and may be NULL only
- * when K == 0 (A, B).  C must not overlap A or B.
+ * 16 B for TSG_C128, 4 B for TSG_R32 and TSG_R32_ACC32, 8 B for TSG_C64 and
+ * TSG_C64_ACC32) and may be NULL only when K == 0 (A, B).  C must not
+ * overlap A or B.
  *
  * Arithmetic: binary64 fused multiply-adds for TSG_R64 / TSG_C128.  For the
  * precision form (TSG_R32 / TSG_C64) the binary32 values are widened exactly
@@ -102,6 +109,13 @@ typedef enum {
  * make it), and the products are accumulated in binary64, as is the
  * reduction across threads and blocks.  The result differs from the binary64
  * sum of the stored binary32 values only by binary64 rounding.
+ * TSG_R32_ACC32 / TSG_C64_ACC32: binary32 products summed in binary32 over
+ * stretches of at most 32 rows of a thread, each stretch sum then added in
+ * binary64; every entry is within c 2^-24 sum_k |op(a_km)| |b_kn| of the
+ * exact sum of the stored values, c = 34 (real) or 66 (each part of a
+ * complex entry, which sums two real products per row).  Where binary64
+ * arithmetic on the widened values is as fast, the library uses it instead
+ * (more accurate, same bound).
  */
 tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
                        const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -143,9 +157,13 @@ tsg_status tsg_tsmttsm_noalloc(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, in
  * A, lda   lda >= M.     C, ldc  ldc >= N (C is M x N).     B, ldb  ldb >= N.
  * Alignment as for tsg_tsmttsm.  B must not overlap A or C.
  *
- * Arithmetic: binary64 fused multiply-adds; for the precision form the
+ * Arithmetic: binary64 fused multiply-adds; for TSG_R32 / TSG_C64 the
  * binary32 inputs are widened exactly, the sum over m is taken in binary64
- * and the result is rounded once to binary32.
+ * and the result is rounded once to binary32.  TSG_R32_ACC32 /
+ * TSG_C64_ACC32: C is rounded to binary32 and the sum over m (at most 64
+ * products) taken in binary32, alpha and beta B in binary64, the result
+ * rounded once to binary32: within (M + 3) 2^-24 sum_m |a_km| |c_mn| plus
+ * one binary32 rounding of the result (per real part; complex: 2M + 3).
  */
 tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N,
                     const void *A, int64_t lda, const void *C, int64_t ldc,
@@ -170,14 +188,17 @@ tsg_status tsg_tsmm_op(tsg_dtype dt, int32_t conjA, tsg_op opC, int64_t K, int32
  * Classical Gram-Schmidt of a block W against an orthonormal basis V needs
  * both products (Section 1.2): C = V^T W, then W <- W - V C.  The batched form
  * runs that step for `count` independent instances (real binary64; each with
- * its own K_i, M_i <= 64, N_i <= 16) in ONE persistent kernel launch.  A
- * device work queue holds first every instance's K-slab items (TSMTTSM
- * partial sums), then every row-slab item (the TSMM update); the last slab
- * item of an instance folds its partials in a fixed order into C_i and marks
- * the instance ready, and an update item starts once its instance is ready.
- * Because all first-phase items are queued before any update item, a waiting
- * update never blocks the work it waits for.  Results are deterministic: the
- * slab boundaries and every summation order are fixed by the plan, not by
+ * its own K_i, M_i <= 64, N_i <= 16; 1 <= count <= 1024) in ONE persistent
+ * kernel launch over a device work queue.  A one-block set-up kernel builds
+ * the queue on the device: instances ordered by decreasing input size
+ * K_i (M_i + N_i), each cut into K-slab items (TSMTTSM partial sums of about
+ * 4 MiB of input, at most 256 per instance) followed, one instance later,
+ * by its row-slab items (the TSMM update).  The last slab item of an
+ * instance to finish folds the instance's partials in slab order into C_i
+ * and marks it ready; an update item starts once its instance is ready.
+ * Every item an update waits for precedes it in the queue and never waits
+ * itself, so the launch cannot deadlock.  Results are deterministic: the
+ * slab boundaries and every summation order are fixed by the queue, not by
  * which block takes which item.  C_i is computed in binary64 by matrix-core
  * products of four rows, summed over the slab's rows, then over slabs in
  * order; the update is W <- W + V (-C) with the same products.
@@ -199,19 +220,48 @@ typedef struct {
 
 typedef struct tsg_orth_plan_t *tsg_orth_plan;
 
-/* Build a plan for `count` >= 1 instances (host array of descriptors, read
- * only during the call) on the current device: validates them, uploads the
- * descriptors and the work-item table, allocates the plan's workspace
- * (partial sums, counters, flags) and captures one launch into a hipGraph on
- * a private stream.  rows_per_item > 0 fixes the slab height of every
- * instance; <= 0 picks it per instance (about 4 MiB of input per slab, at
- * most 256 slabs per instance) and cuts the updates at the end of the queue
- * into half and quarter slabs.  Instances are queued largest first.
+/*
+ * One batched orthogonalisation step (Section 1.2) for `count` instances
+ * whose descriptors lie in DEVICE memory (d_descs, 8-byte aligned, read by
+ * the set-up kernel on the stream, so they may be written by earlier work on
+ * the same stream).  `workspace` is caller-owned device memory of ws_bytes
+ * bytes, 256-byte aligned; tsg_workspace_size(TSG_KIND_ORTH, TSG_R64, K, M,
+ * N, count) gives enough for any `count` instances with K_i <= K, M_i <= M
+ * and N_i <= N and contiguous rows.  Two kernel launches on `stream` (the
+ * set-up kernel, then the persistent kernel); no allocation, no host
+ * synchronisation, so the call can be captured into a graph and replayed.
+ * The workspace holds the queue and partial sums of one call: calls that
+ * share a workspace must not overlap in time.
+ * Host-side errors (nothing enqueued): TSG_E_ARG (null pointers, count < 1,
+ * misaligned workspace or descriptors, ws_bytes below the queue's own
+ * size), TSG_E_UNSUPPORTED (count > 1024), TSG_E_HIP.  Device-side checks of
+ * the descriptors (as listed for tsg_orth_plan_create) and of the workspace
+ * capacity leave every C_i and W_i untouched and are reported by
+ * tsg_orth_batched_check.
+ */
+tsg_status tsg_orth_batched(const tsg_orth_desc *d_descs, int32_t count, void *workspace, size_t ws_bytes,
+                            void *stream);
+/* Waits for the device, then reports the outcome of the last tsg_orth_batched
+ * call on `workspace` and clears it: TSG_OK; TSG_E_ARG (a descriptor failed
+ * the device-side checks: nothing was done); TSG_E_NOMEM (the batch needs
+ * more workspace: nothing was done); TSG_E_HIP (an update waited past its
+ * spin limit: results invalid). */
+tsg_status tsg_orth_batched_check(void *workspace);
+
+/* Build a plan for `count` instances (1..1024; host array of descriptors,
+ * read only during the call) on the current device: validates them on the
+ * host, allocates the plan's workspace, uploads the descriptors, runs the
+ * set-up kernel once (queue as for tsg_orth_batched) and captures one launch
+ * of the persistent kernel into a hipGraph on a private stream.
+ * rows_per_item > 0 fixes the slab height of every instance; <= 0 picks it
+ * per instance (about 4 MiB of input per slab, at most 256 slabs per
+ * instance) and cuts the updates at the end of the queue into half and
+ * quarter slabs.
  * Errors: TSG_E_ARG (null plan/descs, count < 1, K_i < 0, M_i or N_i < 1,
  * ld too small, null or misaligned pointer with K_i > 0, null C_i),
- * TSG_E_UNSUPPORTED (M_i > 64, N_i > 16, slab height > 2^30), TSG_E_NOMEM,
- * TSG_E_HIP.  Allocates: never call it while a stream is being captured.
- * `stream` is unused (reserved). */
+ * TSG_E_UNSUPPORTED (count > 1024, M_i > 64, N_i > 16, slab height too large
+ * for the leading dimensions), TSG_E_NOMEM, TSG_E_HIP.  Allocates: never
+ * call it while a stream is being captured.  `stream` is unused (reserved). */
 tsg_status tsg_orth_plan_create(tsg_orth_plan *plan, int32_t count, const tsg_orth_desc *descs,
                                 int64_t rows_per_item, void *stream);
 /* Replay the plan's graph on `stream` (a stream of the plan's device;
@@ -240,8 +290,20 @@ void tsg_orth_plan_destroy(tsg_orth_plan plan);
  * being captured and the workspace is too small. */
 tsg_status tsg_reserve(tsg_dtype dt, int64_t K, int32_t M, int32_t N, void *stream);
 
-/* Bytes of workspace a TSMTTSM of this shape uses on the current device. */
-size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N);
+/* Operations whose workspace tsg_workspace_size reports. */
+typedef enum {
+    TSG_KIND_TSMTTSM = 0,  /* tsg_tsmttsm: per-block partial sums of one launch        */
+    TSG_KIND_TSMM = 1,     /* tsg_tsmm: none (0 bytes)                                 */
+    TSG_KIND_ORTH = 2      /* tsg_orth_batched: queue and partial sums of one call     */
+} tsg_op_kind;
+
+/* Bytes of workspace an operation uses on the current device:
+ * TSG_KIND_TSMTTSM: a TSMTTSM of shape (K, M, N) and storage type dt (count
+ * ignored) -- what tsg_tsmttsm keeps per stream and tsg_tsmttsm_noalloc
+ * needs of its scratch;  TSG_KIND_TSMM: 0;  TSG_KIND_ORTH (dt = TSG_R64): a
+ * tsg_orth_batched call of `count` instances with K_i <= K, M_i <= M,
+ * N_i <= N.  Returns 0 for shapes outside the supported range. */
+size_t tsg_workspace_size(int32_t op_kind, tsg_dtype dt, int64_t K, int32_t M, int32_t N, int32_t count);
 
 /* Optional set-up for `device` (queries device properties); calls do it
  * lazily otherwise.  Returns TSG_E_HIP without a usable device. */
@@ -271,6 +333,43 @@ const char *tsg_kernel_name(int32_t op_kind, tsg_dtype dt, int32_t conj, int32_t
  * them with events.  tsg_stream_read keeps a small internal sink buffer. */
 tsg_status tsg_stream_read(const void *x, size_t bytes, void *stream);
 tsg_status tsg_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* The grid of Table 1 (Section 1.6): bandwidth against occupancy and loads in
+ * flight, extended by a write stream.  Reads x in chunks of 256 threads x
+ * loads_in_flight (1, 2, 4, 8 or 16) 16-byte non-temporal loads issued
+ * together, and per chunk writes its share of y (y_bytes / chunks, from the
+ * loaded values; stream_stores != 0: non-temporal stores, else cached), so
+ * y_bytes : x_bytes sets the write:read ratio (0: read only, as Table 1).
+ * blocks_per_cu (1..32) blocks of 256 threads per compute unit set the
+ * occupancy.  *moved (may be NULL) receives the bytes read and written.
+ * x, y device pointers, 16-byte aligned; x_bytes must cover one chunk.
+ * Asynchronous; time it with events.  TSG_E_ARG on invalid arguments. */
+tsg_status tsg_stream_probe(const void *x, size_t x_bytes, void *y, size_t y_bytes, int32_t blocks_per_cu,
+                            int32_t loads_in_flight, int32_t stream_stores, size_t *moved, void *stream);
+
+/* Peak arithmetic rates (Section 1.6 computes the FP64 peak from the clock
+ * and unit counts; these measure it): register-only loops with independent
+ * accumulator chains on the matrix cores (binary64 or binary32 16x16x4
+ * products), on the vector unit (binary64 FMA), or both from the same waves.
+ * blocks_per_cu (1..32) blocks of 256 threads per compute unit, `iters` loop
+ * iterations; *flops (may be NULL) receives the flops of the launch.
+ * Asynchronous; time it with events. */
+typedef enum {
+    TSG_PEAK_MFMA_F64 = 0,
+    TSG_PEAK_VALU_F64 = 1,
+    TSG_PEAK_MFMA_F32 = 2,
+    TSG_PEAK_MIXED_F64 = 3
+} tsg_peak_kind;
+tsg_status tsg_peak_probe(int32_t kind, int32_t blocks_per_cu, int64_t iters, double *flops, void *stream);
+
+/* Memory latency by pointer chasing (Section 5.3 measures latency to apply
+ * Little's law): one lane follows next[] from index 0 for `steps` dependent
+ * loads (after 64 warm-up loads).  out[0] = elapsed shader clocks, out[1] =
+ * elapsed ticks of the 100 MHz constant clock, out[2] = the final index (all
+ * device memory, int64).  `next` is a device array of indices into itself
+ * that the caller builds (a random cycle over a working set of the chosen
+ * size).  Asynchronous. */
+tsg_status tsg_latency_probe(const int64_t *next, int64_t steps, int64_t *out, void *stream);
 
 /* ---- tuning hooks (used by the autotuner; not needed for ordinary calls) ----
  * The library holds many generated kernel variants; normally it picks the one

@@ -10,8 +10,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TSG_LIBRARY", os.path.join(HERE, "libtsgemm.so"))
 
-TSG_R64, TSG_C128, TSG_R32, TSG_C64 = 0, 1, 2, 3
+TSG_R64, TSG_C128, TSG_R32, TSG_C64, TSG_R32_ACC32, TSG_C64_ACC32 = 0, 1, 2, 3, 4, 5
 TSG_OP_T, TSG_OP_C, TSG_OP_N = 0, 1, 2
+TSG_KIND_TSMTTSM, TSG_KIND_TSMM, TSG_KIND_ORTH = 0, 1, 2
+TSG_PEAK_MFMA_F64, TSG_PEAK_VALU_F64, TSG_PEAK_MFMA_F32, TSG_PEAK_MIXED_F64 = 0, 1, 2, 3
 TSG_OK, TSG_E_ARG, TSG_E_UNSUPPORTED, TSG_E_NOMEM, TSG_E_HIP, TSG_E_CAPTURE = range(6)
 STATUS_NAMES = {0: "TSG_OK", 1: "TSG_E_ARG", 2: "TSG_E_UNSUPPORTED", 3: "TSG_E_NOMEM", 4: "TSG_E_HIP",
                 5: "TSG_E_CAPTURE"}
@@ -23,6 +25,8 @@ PROTOTYPES = {
     "tsg_tsmttsm_noalloc": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "tsg_tsmm": (_i32, [_i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
     "tsg_tsmm_op": (_i32, [_i32, _i32, _i32, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _dbl, _dbl, _vp]),
+    "tsg_orth_batched": (_i32, [_vp, _i32, _vp, _sz, _vp]),
+    "tsg_orth_batched_check": (_i32, [_vp]),
     "tsg_orth_plan_create": (_i32, [_vp, _i32, _vp, _i64, _vp]),
     "tsg_orth_plan_launch": (_i32, [_vp, _vp]),
     "tsg_orth_plan_run": (_i32, [_vp, _vp]),
@@ -30,7 +34,7 @@ PROTOTYPES = {
     "tsg_orth_plan_set_spin_limit": (_i32, [_vp, ctypes.c_uint32]),
     "tsg_orth_plan_destroy": (None, [_vp]),
     "tsg_reserve": (_i32, [_i32, _i64, _i32, _i32, _vp]),
-    "tsg_workspace_size": (_sz, [_i32, _i64, _i32, _i32]),
+    "tsg_workspace_size": (_sz, [_i32, _i32, _i64, _i32, _i32, _i32]),
     "tsg_init": (_i32, [_i32]),
     "tsg_finalize": (None, []),
     "tsg_status_string": (ctypes.c_char_p, [_i32]),
@@ -38,6 +42,9 @@ PROTOTYPES = {
     "tsg_kernel_name": (ctypes.c_char_p, [_i32, _i32, _i32, _i32, _i32]),
     "tsg_stream_read": (_i32, [_vp, _sz, _vp]),
     "tsg_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
+    "tsg_stream_probe": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, ctypes.POINTER(_sz), _vp]),
+    "tsg_peak_probe": (_i32, [_i32, _i32, _i64, ctypes.POINTER(_dbl), _vp]),
+    "tsg_latency_probe": (_i32, [_vp, _i64, _vp, _vp]),
     "tsg_force_variant": (_i32, [ctypes.c_char_p]),
     "tsg_set_grid_limit": (_i32, [_i32]),
     "tsg_variant_count": (_i32, []),
@@ -105,8 +112,8 @@ def tsg_reserve(dt, K, M, N, stream):
     return lib().tsg_reserve(dt, K, M, N, stream)
 
 
-def tsg_workspace_size(dt, K, M, N):
-    return lib().tsg_workspace_size(dt, K, M, N)
+def tsg_workspace_size(op_kind, dt, K, M, N, count):
+    return lib().tsg_workspace_size(op_kind, dt, K, M, N, count)
 
 
 def tsg_init(device):
@@ -151,6 +158,33 @@ def tsg_stream_read(x, nbytes, stream):
 
 def tsg_stream_copy(src, dst, nbytes, stream):
     return lib().tsg_stream_copy(src, dst, nbytes, stream)
+
+
+def tsg_stream_probe(x, x_bytes, y, y_bytes, blocks_per_cu, loads_in_flight, stream_stores, stream):
+    """Returns (status, bytes moved)."""
+    moved = _sz(0)
+    st = lib().tsg_stream_probe(x, x_bytes, y, y_bytes, blocks_per_cu, loads_in_flight, stream_stores,
+                                ctypes.byref(moved), stream)
+    return st, moved.value
+
+
+def tsg_peak_probe(kind, blocks_per_cu, iters, stream):
+    """Returns (status, flops of the launch)."""
+    fl = _dbl(0.0)
+    st = lib().tsg_peak_probe(kind, blocks_per_cu, iters, ctypes.byref(fl), stream)
+    return st, fl.value
+
+
+def tsg_latency_probe(next_ptr, steps, out_ptr, stream):
+    return lib().tsg_latency_probe(next_ptr, steps, out_ptr, stream)
+
+
+def tsg_orth_batched(d_descs, count, workspace, ws_bytes, stream):
+    return lib().tsg_orth_batched(d_descs, count, workspace, ws_bytes, stream)
+
+
+def tsg_orth_batched_check(workspace):
+    return lib().tsg_orth_batched_check(workspace)
 
 
 def tsg_orth_plan_create(descs, rows_per_item, stream):

@@ -26,12 +26,28 @@ def _stream(dev):
     return torch.cuda.current_stream(dev).cuda_stream
 
 
-def tsmttsm(A, B, op="T", out=None):
+def _dtype(t, acc):
+    """ABI storage/arithmetic type of tensor dtype t; acc='f32' selects binary32
+    arithmetic for binary32 storage (float32 / complex64)."""
+    if acc not in ("f64", "f32"):
+        raise ValueError("acc must be 'f64' or 'f32'")
+    if acc == "f32":
+        if t == torch.float32:
+            return _lib.TSG_R32_ACC32
+        if t == torch.complex64:
+            return _lib.TSG_C64_ACC32
+        raise TypeError("acc='f32' needs float32 or complex64 storage")
+    return _DT[t]
+
+
+def tsmttsm(A, B, op="T", out=None, acc="f64"):
     """C = op(A)^T B for tall row-major A (K x M) and B (K x N) on the GPU.
 
     op: 'T' (transpose) or 'C' (conjugate transpose, complex only).
     float32 / complex64 inputs are the precision form; C is always float64 /
-    complex128.  ``out`` may be an (M x N) row-major tensor to write into.
+    complex128.  acc='f32' (binary32 storage only) sums binary32 products in
+    binary32 over stretches of 32 rows, binary64 beyond.  ``out`` may be an
+    (M x N) row-major tensor to write into.
     """
     if A.dtype != B.dtype or A.dtype not in _DT:
         raise TypeError("A and B must share one of float64, complex128, float32, complex64")
@@ -46,13 +62,13 @@ def tsmttsm(A, B, op="T", out=None):
     elif out.shape != (M, N) or out.dtype != _SMALL[A.dtype] or out.device != A.device:
         raise ValueError("out must be an (M, N) %s tensor on %s" % (_SMALL[A.dtype], A.device))
     with torch.cuda.device(A.device):
-        _lib.check(_lib.tsg_tsmttsm(_DT[A.dtype], _lib.TSG_OP_C if op == "C" else _lib.TSG_OP_T, K, M, N,
+        _lib.check(_lib.tsg_tsmttsm(_dtype(A.dtype, acc), _lib.TSG_OP_C if op == "C" else _lib.TSG_OP_T, K, M, N,
                                     A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
                                     out.data_ptr(), _ld(out, "out"), _stream(A.device)))
     return out
 
 
-def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False, opC="N"):
+def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False, opC="N", acc="f64"):
     """B = alpha * op(A) opC(C) + beta * out for tall A (K x M).
 
     opC: 'N' uses C (M x N); 'T' uses C^T and 'C' uses C^H of a stored
@@ -78,15 +94,15 @@ def tsmm(A, C, out=None, alpha=1.0, beta=0.0, conjA=False, opC="N"):
         raise ValueError("out must be a (K, N) %s tensor on %s" % (A.dtype, A.device))
     op = {"N": _lib.TSG_OP_N, "T": _lib.TSG_OP_T, "C": _lib.TSG_OP_C}[opC]
     with torch.cuda.device(A.device):
-        _lib.check(_lib.tsg_tsmm_op(_DT[A.dtype], int(bool(conjA)), op, K, M, N, A.data_ptr(), _ld(A, "A"),
+        _lib.check(_lib.tsg_tsmm_op(_dtype(A.dtype, acc), int(bool(conjA)), op, K, M, N, A.data_ptr(), _ld(A, "A"),
                                     C.data_ptr(), _ld(C, "C"), out.data_ptr(), _ld(out, "out"),
                                     float(alpha), float(beta), _stream(A.device)))
     return out
 
 
-def kernel_name(op, dtype, M, N, conj=False):
+def kernel_name(op, dtype, M, N, conj=False, acc="f64"):
     """Name of the kernel variant the library launches for this problem."""
-    return _lib.tsg_kernel_name(0 if op == "tsmttsm" else 1, _DT[dtype], int(conj), M, N)
+    return _lib.tsg_kernel_name(0 if op == "tsmttsm" else 1, _dtype(dtype, acc), int(conj), M, N)
 
 
 class OrthPlan:
@@ -162,6 +178,63 @@ class OrthPlan:
             self.close()
         except Exception:
             pass
+
+
+class OrthBatch:
+    """The batched orthogonalisation through ``tsg_orth_batched``: the
+    descriptors live in device memory and every ``run()`` is one call of two
+    kernel launches on the current stream, with no allocation and no host
+    synchronisation (it can be captured into a graph).  ``workspace`` may be
+    a caller's uint8 tensor of at least ``workspace_bytes`` bytes (256-byte
+    aligned); by default one is allocated here.  Same tensors and rules as
+    ``OrthPlan``; calls sharing a workspace must not overlap."""
+
+    def __init__(self, pairs, C=None, workspace=None):
+        if not pairs:
+            raise ValueError("need at least one (V, W) pair")
+        dev = pairs[0][0].device
+        self.device = dev
+        self.pairs = list(pairs)
+        self.C = []
+        descs = []
+        kmax = mmax = nmax = 1
+        for i, (V, W) in enumerate(self.pairs):
+            if V.dtype != torch.float64 or W.dtype != torch.float64:
+                raise TypeError("instance %d: V and W must be float64" % i)
+            if V.device != dev or W.device != dev or V.dim() != 2 or W.dim() != 2 or V.shape[0] != W.shape[0]:
+                raise ValueError("instance %d: V (K x M) and W (K x N) on %s with the same rows" % (i, dev))
+            K, M = V.shape
+            N = W.shape[1]
+            Ci = C[i] if C is not None else torch.empty((M, N), dtype=torch.float64, device=dev)
+            self.C.append(Ci)
+            descs.append(_lib.tsg_orth_desc(K, M, N, V.data_ptr(), _ld(V, "V"), W.data_ptr(), _ld(W, "W"),
+                                            Ci.data_ptr(), _ld(Ci, "C")))
+            kmax, mmax, nmax = max(kmax, K), max(mmax, M), max(nmax, N)
+        raw = (_lib.tsg_orth_desc * len(descs))(*descs)
+        host = torch.frombuffer(bytearray(bytes(raw)), dtype=torch.uint8)
+        self.d_descs = host.to(dev)
+        with torch.cuda.device(dev):
+            self.workspace_bytes = _lib.tsg_workspace_size(_lib.TSG_KIND_ORTH, _lib.TSG_R64, kmax, mmax, nmax,
+                                                           len(descs))
+        if self.workspace_bytes == 0:
+            raise ValueError("widths or instance count outside the supported range")
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+            off = (-workspace.data_ptr()) % 256
+            workspace = workspace[off:off + self.workspace_bytes]
+        self.workspace = workspace
+
+    def run(self):
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_batched(self.d_descs.data_ptr(), len(self.pairs), self.workspace.data_ptr(),
+                                             self.workspace.numel(), _stream(self.device)))
+        return self.C
+
+    def check(self):
+        """Wait for the device; raise if the last call was rejected on the
+        device or a wait inside it gave up."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.tsg_orth_batched_check(self.workspace.data_ptr()))
 
 
 def orth_batched(pairs, rows_per_item=0):

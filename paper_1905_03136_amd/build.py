@@ -32,8 +32,9 @@ CFLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 
-HEADERS = [os.path.join(CSRC, h) for h in ("tsg_device.hpp", "tsg_kernels.hpp", "tsg_registry.hpp")] + \
-    [os.path.join(ROOT, "include", "tsgemm.h")]
+# headers every unit includes; the C ABI header only the hand-written units
+HEADERS = [os.path.join(CSRC, h) for h in ("tsg_device.hpp", "tsg_kernels.hpp", "tsg_registry.hpp")]
+ABI_HEADER = os.path.join(ROOT, "include", "tsgemm.h")
 TUNE_LIB = os.path.join(HERE, "libtsgemm_tune.so")
 
 
@@ -123,10 +124,14 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
         if o not in keep:
             os.remove(o)
     jobs = jobs or min(8, os.cpu_count() or 1)
+    # objects built with other flags are stale (the flags are kept beside them)
+    stamp = os.path.join(OBJD, "flags.txt")
+    flags = " ".join([HIPCC] + CFLAGS + list(extra_flags))
+    same_flags = os.path.exists(stamp) and open(stamp).read() == flags
 
     def compile_all(sources, what):
         todo = [(s, obj_of[s]) for s in sources
-                if _stale(obj_of[s], [s] + HEADERS + [os.path.abspath(__file__)])
+                if not same_flags or _stale(obj_of[s], [s] + HEADERS + ([] if s in units else [ABI_HEADER]))
                 or (s in units and not os.path.exists(obj_of[s] + SPILLS))]
         if not todo:
             return
@@ -149,6 +154,8 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
         from paper_1905_03136_amd import codegen
         codegen.emit(gen_dir, variants, exclude=spilled)
     compile_all([table], "registry table")
+    with open(stamp, "w") as f:
+        f.write(flags)
     objs = [obj_of[s] for s in srcs] + [obj_of[table]]
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", lib_path + ".tmp", *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

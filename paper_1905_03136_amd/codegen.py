@@ -18,9 +18,16 @@ import math
 import os
 
 # storage types of the tall matrices: (ABI id, complex).  r32 / c64 are the
-# precision form (binary32 storage, binary64 arithmetic on widened values).
-DTYPES = {"r64": (0, False), "c128": (1, True), "r32": (2, False), "c64": (3, True)}
-F32_DTYPES = ("r32", "c64")
+# precision form with binary64 arithmetic on the widened values; r32a / c64a
+# the precision form with binary32 products summed in binary32 over stretches
+# of 32 rows (binary64 beyond), whose kernels may also be the binary64-
+# arithmetic ones of r32 / c64 (more accurate) where those are faster.
+DTYPES = {"r64": (0, False), "c128": (1, True), "r32": (2, False), "c64": (3, True),
+          "r32a": (4, False), "c64a": (5, True)}
+F32_DTYPES = ("r32", "c64", "r32a", "c64a")
+A32_DTYPES = ("r32a", "c64a")
+# binary64-arithmetic storage twin of a binary32-arithmetic type
+A32_TWIN = {"r32a": "r32", "c64a": "c64"}
 OPS = {"tsmttsm": 0, "tsmm": 1}
 
 # widths of the plain sweep and the square widths of the target range
@@ -28,10 +35,17 @@ GRADED = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8),
 SQUARE_ALL = [(w, w) for w in range(1, 65)]
 # pre-generated widths of the precision form (others use run-time-width variants)
 PRECISION = GRADED
+# widths whose every candidate the default build compiles into the tuning
+# library (the sweep widths and two odd pairs with guards on every tile)
+TUNE_WIDTHS = GRADED + [(3, 5), (13, 7)]
 
 
 def is_f32(dt):
     return dt in F32_DTYPES
+
+
+def is_a32(dt):
+    return dt in A32_DTYPES
 
 WPB = 4  # waves per block
 
@@ -60,10 +74,62 @@ def candidates(op, dt, M, N):
     a register model (the gfx950 analogue of the paper's register estimate
     2 (T_M T_N + 2 (T_M + T_N) + 8), Section 5.2): FP64 operands live in the
     256 architectural VGPRs, MFMA accumulators may use the AGPRs.  The
-    binary32-storage types use the matrix-core kinds only."""
+    binary32-storage types use the matrix-core kinds only; the binary32-
+    arithmetic types add the kernels with binary32 products (kind "a32") to
+    the candidates of their binary64-arithmetic twin."""
+    if is_a32(dt):
+        return candidates(op, A32_TWIN[dt], M, N) + _a32_candidates(op, dt, M, N)
     out = _candidates(op, dt, M, N)
     if is_f32(dt):
         out = [c for c in out if c["kind"] != "valu" and not c.get("VA")]
+    return out
+
+
+def _a32_candidates(op, dt, M, N):
+    """Binary32-product kernels: the blocked matrix-core mappings with binary32
+    operands.  Register model in binary64 units per lane: binary64 stretch
+    sums (TSMTTSM) plus binary32 products (half a unit each) plus operands;
+    kernels that still spill are dropped by the build."""
+    cw = 2 if DTYPES[dt][1] else 1
+    cplx = DTYPES[dt][1]
+    out = []
+    if op == "tsmttsm":
+        if M <= 8 and N <= 8:
+            return out
+        mbt, nb = _ceil(M, 16), _ceil(N, 16)
+        fl = max(f for f in (1, 2, 4) if (M * cw) % f == 0 and (N * cw) % f == 0)
+        for mw in (1, 2, 4):
+            if (mbt % mw and mw > 1) or mw > mbt:
+                continue
+            mb = _ceil(mbt, mw)
+            acc = mb * nb * 4 * cw * 1.5
+            for w in (4, 8):
+                if w % mw:
+                    continue
+                for u in (1, 2, 4):
+                    for nbuf in (2, 3):
+                        ops = nbuf * u * (mb + nb) * cw / 2
+                        if nbuf > 2 and u > 2:
+                            continue
+                        if acc + ops > (200 if w == 4 else 110):
+                            continue
+                        out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf))
+                        if mw == 1 and u <= 2:
+                            out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf, FL=fl))
+        return out
+    if M < 3 and N < 16:
+        return out
+    ms, nb = _ceil(M, 4), _ceil(N, 16)
+    fl = max(f for f in (1, 2, 4) if M % f == 0)
+    for u in (1, 2, 4):
+        for w in (4, 8):
+            for nbuf in (2, 3):
+                ops = (nbuf * u * ms * cw + u * nb * 4 * cw) / 2
+                if ops > (48 if w == 8 else 80) or (nbuf > 2 and u > 2):
+                    continue
+                out.append(dict(kind="a32", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
+                if not cplx:
+                    out.append(dict(kind="a32", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, FL=fl))
     return out
 
 
@@ -214,6 +280,16 @@ def default_config(op, dt, M, N):
     measured this (op, dt, M, N): row packing on the matrix cores for narrow
     widths, the blocked matrix-core kernels otherwise."""
     cw = 2 if DTYPES[dt][1] else 1
+    if is_a32(dt):
+        # binary32 products wherever the matrix-core mappings apply
+        if op == "tsmttsm" and (M > 8 or N > 8):
+            mbt, nb = _ceil(M, 16), _ceil(N, 16)
+            mw = 1 if mbt * nb * cw <= 8 else 2
+            return dict(kind="a32", MB=_ceil(mbt, mw), NB=nb, MW=mw, U=2, WPB=WPB)
+        if op == "tsmm" and M >= 3:
+            ms, nb = _ceil(M, 4), _ceil(N, 16)
+            return dict(kind="a32", MS=ms, NB=nb, U=2 if ms * nb * cw <= 32 else 1, WPB=WPB)
+        return default_config(op, A32_TWIN[dt], M, N)
     if op == "tsmttsm":
         if M <= 16 and N <= 16 and (M < 16 or N < 16):
             return dict(kind="packed", U=4, WPB=WPB)
@@ -275,6 +351,8 @@ def generic_variants():
     from the smallest covering shape to the largest."""
     out = []
     for dt, (_, cplx) in DTYPES.items():
+        if is_a32(dt):
+            continue  # served by the run-time-width variants of the binary64-arithmetic twin
         cw = 2 if cplx else 1
         # TSMTTSM: row packing up to 16, then blocked matrix-core kernels
         out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16, maxN=16,
@@ -317,7 +395,10 @@ def tuning_variants(widths):
             for (M, N) in widths:
                 if is_f32(dt) and (M, N) not in PRECISION:
                     continue
-                for c in candidates(op, dt, M, N):
+                # binary32-arithmetic types: only their own kernels (the
+                # binary64-arithmetic ones are timed under the twin type)
+                cands = _a32_candidates(op, dt, M, N) if is_a32(dt) else candidates(op, dt, M, N)
+                for c in cands:
                     v = dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=c)
                     name = variant_name(v)
                     if name not in seen:
@@ -368,7 +449,7 @@ def exact_variants(widths, tuned=None):
                 for c in cfgs:
                     # TSMM on the matrix cores: a twin reading the old B with A
                     # for calls with beta != 0, ahead of the one serving beta = 0
-                    if op == "tsmm" and c["kind"] == "mfma":
+                    if op == "tsmm" and c["kind"] in ("mfma", "a32"):
                         out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=dict(c, RB=1)))
                     out.append(dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=c))
     return out
@@ -382,6 +463,10 @@ def variant_name(v):
         tag = "valu_u%d" % c["U"]
     elif c["kind"] == "packed":
         tag = "packed_u%d" % c["U"]
+    elif c["kind"] == "a32" and v["op"] == "tsmttsm":
+        tag = "a32_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
+    elif c["kind"] == "a32":
+        tag = "a32_s%dn%d_u%d" % (c["MS"], c["NB"], c["U"])
     elif v["op"] == "tsmttsm":
         tag = "mfma_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
     else:
@@ -413,6 +498,12 @@ def _template(v):
     f32 = "true" if is_f32(v["dt"]) else "false"
     if c["kind"] == "packed":
         return "tsg::%s_packed<%d, %d, %d, %s, %d, %d, %s>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf, f32)
+    if c["kind"] == "a32" and v["op"] == "tsmttsm":
+        return "tsg::tsmttsm_a32<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %d>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), c.get("FL", 0))
+    if c["kind"] == "a32":
+        return "tsg::tsmm_a32<%d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
+            M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, c.get("FL", 0), "true" if c.get("RB") else "false")
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
@@ -437,7 +528,7 @@ def rows_per_tile(v):
     if c["kind"] == "packed":
         return (4 if v["op"] == "tsmttsm" else 16) * c["U"] * c["WPB"]
     if v["op"] == "tsmttsm":
-        return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])
+        return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])  # mfma, a32
     return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 16 * c["U"] * c["WPB"]
 
 
@@ -460,7 +551,7 @@ def _record(v, fn):
     # slab reads need 16-byte alignment (and, with lda = M, an even width) where
     # one lane load spans two or more elements (a complex element is two reals)
     slab_pairs = c.get("FL", 0) // (2 if DTYPES[v["dt"]][1] else 1) >= 2
-    pair_a = int(c["kind"] in ("valu", "mfma") and (bool(c.get("VA")) or slab_pairs))
+    pair_a = int(c["kind"] in ("valu", "mfma", "a32") and (bool(c.get("VA")) or slab_pairs))
     pair_x = int((c["kind"] == "valu" and bool(c.get("VB"))) or (v["op"] == "tsmttsm" and slab_pairs))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)

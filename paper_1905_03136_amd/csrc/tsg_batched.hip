@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <new>
 #include <numeric>
@@ -45,6 +46,7 @@ constexpr unsigned kDefaultSpin = 1u << 23;   // sleeps of ~0.2 us: about 2 s
 constexpr int64_t kItemBytes = 4 << 20;       // input bytes of one slab (automatic sizing; 4 MB measured
                                               // 3% faster than 2 MB and 8 MB on the 64-instance workload)
 constexpr int64_t kMaxSlabs = 256;            // slabs per instance (bounds the fold)
+constexpr int kDefaultLag = 0;                // instances between an instance's slab items and its updates (0: all)
 
 struct Item {
     int64_t row0;      // first row of the slab
@@ -69,11 +71,18 @@ struct DevDesc {
     int32_t pad;
 };
 
+// Error bits of Ctrl::err.
+constexpr unsigned kErrSpin = 1u;      // an update waited past the spin limit (results invalid)
+constexpr unsigned kErrDesc = 2u;      // a descriptor failed the device-side checks (nothing was done)
+constexpr unsigned kErrSpace = 4u;     // the queue or the partial sums do not fit the workspace (nothing was done)
+
 struct Ctrl {
     unsigned head;   // next queue position
     unsigned done;   // blocks that have left the queue loop
-    unsigned err;    // a wait ran past the spin limit
+    unsigned err;    // error bits (kErr*)
     unsigned spin;   // spin limit
+    unsigned total;  // items in the queue, written by the set-up kernel
+    unsigned pad[3];
 };
 
 __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c)
@@ -575,13 +584,15 @@ __device__ __attribute__((noinline)) void run_update(const Item* items, const De
 
 // Two waves per SIMD: every path fits in 256 registers without spilling.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
-orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ items, int total,
+orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ items,
                 double* __restrict__ parts, unsigned* __restrict__ cnt, unsigned* __restrict__ ready,
                 Ctrl* __restrict__ ctrl, int count)
 {
     __shared__ int s_q, s_last;
     double* lds = g_lds;
     const int tid = threadIdx.x;
+    // written by the set-up kernel earlier on the stream (0 when it rejected the batch)
+    const int total = (int)__builtin_amdgcn_readfirstlane(ctrl->total);
     while (true) {
         if (tid == 0)
             s_q = (int)__hip_atomic_fetch_add(&ctrl->head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -700,24 +711,251 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
     }
 }
 
+// ------------------------------------------------------------ work queue
+// Slab height of an instance: rows_fixed if positive, else about kItemBytes
+// of input per slab and at most kMaxSlabs slabs; never more rows than keep
+// the byte offsets inside a slab (plus one step past its end) below 2^31.
+// Returns 0 if no height fits (leading dimensions too large).  Shared by the
+// host (workspace sizes, plan checks) and the set-up kernel.
+__host__ __device__ inline int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
+
+__host__ __device__ inline int64_t slab_limit(int64_t ldv, int64_t ldw)
+{
+    const int64_t ld = ldv > ldw ? ldv : ldw;
+    return ((((int64_t)1 << 31) / (8 * ld)) - 128) / 16 * 16;
+}
+
+__host__ __device__ inline int64_t slab_rows(int64_t K, int M, int N, int64_t ldv, int64_t ldw, int64_t rows_fixed)
+{
+    const int64_t lim = slab_limit(ldv, ldw);
+    int64_t R = rows_fixed;
+    if (R <= 0) {
+        const int64_t want = round16(kItemBytes / (8 * (int64_t)(M + N)));
+        R = want > 16 ? want : 16;
+        const int64_t few = round16((K + kMaxSlabs - 1) / kMaxSlabs);
+        R = R > few ? R : few;
+        R = R < lim ? R : lim;
+    }
+    return (R >= 1 && R <= lim) ? R : 0;
+}
+
+// Rows of one update item cut from a slab of nr rows into about f pieces
+// (f = 1: the whole slab).
+__host__ __device__ inline int64_t update_piece(int64_t nr, int f)
+{
+    if (f <= 1) return nr;
+    const int64_t p = round16((nr + f - 1) / f);
+    return p > 16 ? p : 16;
+}
+
+// Items per instance that a workspace sized by tsg_workspace_size holds:
+// kMaxSlabs slab items and, at the end of the queue, up to four update
+// pieces per slab.
+constexpr int64_t kItemsPerInstance = 5 * kMaxSlabs;
+constexpr int kMaxCount = 1024;  // instances per call (one set-up block, one thread each)
+
+// Byte layout of a workspace: control words, descriptors, arrival counters
+// and ready flags, the item queue, the partial sums.  Regions start at
+// multiples of 256 bytes.
+struct Layout {
+    size_t ctrl, descs, flags, items, parts, bytes;
+    int64_t max_items, max_parts;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+__host__ __device__ inline Layout make_layout(int count, int64_t max_items, int64_t max_parts)
+{
+    Layout L{};
+    L.ctrl = 0;
+    L.descs = align256(sizeof(Ctrl));
+    L.flags = L.descs + align256(sizeof(DevDesc) * (size_t)count);
+    L.items = L.flags + align256(sizeof(unsigned) * 2 * (size_t)count);
+    L.parts = L.items + align256(sizeof(Item) * (size_t)max_items);
+    L.bytes = L.parts + sizeof(double) * (size_t)(max_parts > 0 ? max_parts : 1);
+    L.max_items = max_items;
+    L.max_parts = max_parts;
+    return L;
+}
+
+// Set-up kernel (one block of kMaxCount threads): checks the descriptors,
+// orders the instances by decreasing input size K (M + N) (ties by index),
+// cuts them into slabs, places the partial sums, writes the item queue and
+// clears the counters, flags and queue head, all on the device, so a call
+// with descriptors in device memory needs no host round trip and can be
+// captured into a graph.  Queue order: the slab items of instance r (rank
+// in size order) are followed by those of instance r + lag, then the update
+// items of instance r (lag >= count: every slab item before any update
+// item).  An update item waits only for slab items of its own instance, all
+// of which precede it in the queue and never wait, so the persistent kernel
+// cannot deadlock whatever the lag.  With automatic slab heights the updates
+// at the end of the queue are cut finer (the instance whose later update
+// items number fewer than `resident` into quarter slabs, fewer than three
+// times that into half slabs), so the blocks still running after the queue
+// drains hold short items.
+__global__ void __launch_bounds__(kMaxCount)
+orth_setup(const tsg_orth_desc* __restrict__ in, int count, int64_t rows_fixed, int lag, int resident,
+           unsigned spin, Ctrl* __restrict__ ctrl, DevDesc* __restrict__ dd, unsigned* __restrict__ flags,
+           Item* __restrict__ items, int64_t max_items, int64_t max_parts)
+{
+    // 56 KB: per instance its size key (then K), slab height, first partial
+    // sum, slabs, rank order, queue positions, update pieces, pieces per full
+    // slab, M N and its piece factor
+    __shared__ int64_t s_key[kMaxCount], s_rows[kMaxCount], s_part0[kMaxCount];
+    __shared__ int s_nsl[kMaxCount], s_ord[kMaxCount], s_pos1[kMaxCount], s_pos2[kMaxCount];
+    __shared__ int s_pieces[kMaxCount], s_npf[kMaxCount], s_E[kMaxCount], s_f[kMaxCount];
+    __shared__ unsigned s_err;
+    __shared__ int s_total;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_err = 0u;
+    __syncthreads();
+    tsg_orth_desc x{};
+    if (tid < count) {
+        x = in[tid];
+        const uintptr_t al = reinterpret_cast<uintptr_t>(x.V) | reinterpret_cast<uintptr_t>(x.W) |
+                             reinterpret_cast<uintptr_t>(x.C);
+        bool ok = x.K >= 0 && x.M >= 1 && x.N >= 1 && x.M <= kMaxM && x.N <= kMaxN && x.ldv >= x.M &&
+                  x.ldw >= x.N && x.ldc >= x.N && x.C && (x.K == 0 || (x.V && x.W)) && al % sizeof(double) == 0;
+        const int64_t R = ok ? slab_rows(x.K, x.M, x.N, x.ldv, x.ldw, rows_fixed) : 0;
+        const int64_t nsl = x.K > 0 && R > 0 ? (x.K + R - 1) / R : 1;  // K = 0: one empty slab sets C = 0
+        ok = ok && R > 0 && nsl <= ((int64_t)1 << 24);
+        if (!ok) atomicOr(&s_err, kErrDesc);
+        s_key[tid] = x.K * (int64_t)(x.M + x.N);
+        s_rows[tid] = ok ? R : 1;
+        s_nsl[tid] = ok ? (int)nsl : 1;
+        s_E[tid] = x.M * x.N;
+        flags[tid] = 0u;           // arrival counter
+        flags[count + tid] = 0u;   // ready flag
+    }
+    __syncthreads();
+    // rank by decreasing size, ties by index
+    if (tid < count) {
+        int r = 0;
+        for (int j = 0; j < count; ++j) r += (s_key[j] > s_key[tid]) || (s_key[j] == s_key[tid] && j < tid);
+        s_ord[r] = tid;
+    }
+    __syncthreads();
+    if (tid < count) s_key[tid] = x.K;  // the keys are no longer needed
+    __syncthreads();
+    if (tid == 0) {
+        // update pieces per instance, from the end of the queue backwards
+        int64_t made = 0;
+        for (int r = count - 1; r >= 0; --r) {
+            const int i = s_ord[r];
+            const int64_t K = s_key[i], R = s_rows[i];
+            const int n = s_nsl[i];
+            int64_t pieces = 0, npf = 1;
+            const int f = rows_fixed > 0 ? 1 : made < resident ? 4 : made < 3 * (int64_t)resident ? 2 : 1;
+            if (K > 0) {
+                const int64_t last = K - (int64_t)(n - 1) * R;
+                const int64_t pf = update_piece(R, f), pl = update_piece(last, f);
+                npf = (R + pf - 1) / pf;
+                pieces = (int64_t)(n - 1) * npf + (last + pl - 1) / pl;
+            }
+            s_pieces[i] = (int)min(pieces, (int64_t)1 << 30);
+            s_npf[i] = (int)npf;
+            s_f[i] = f;
+            made += pieces;
+        }
+        // queue positions and partial-sum offsets, largest instance first
+        if (lag < 1) lag = 1;
+        int64_t pos = 0, part = 0;
+        for (int r = 0; r < count + lag; ++r) {
+            if (r < count) {
+                const int i = s_ord[r];
+                s_part0[i] = part;
+                part += (int64_t)s_nsl[i] * s_E[i];
+                s_pos1[i] = (int)min(pos, (int64_t)1 << 30);
+                pos += s_nsl[i];
+            }
+            if (r >= lag && r - lag < count) {
+                const int i = s_ord[r - lag];
+                s_pos2[i] = (int)min(pos, (int64_t)1 << 30);
+                pos += s_pieces[i];
+            }
+        }
+        if (pos > max_items || part > max_parts) s_err |= kErrSpace;
+        s_total = s_err ? 0 : (int)pos;
+    }
+    __syncthreads();
+    if (tid < count) {
+        DevDesc d{};
+        d.K = x.K;
+        d.V = x.V;
+        d.ldv = x.ldv;
+        d.W = x.W;
+        d.ldw = x.ldw;
+        d.C = x.C;
+        d.ldc = x.ldc;
+        d.M = x.M;
+        d.N = x.N;
+        d.part0 = s_part0[tid];
+        d.nparts = s_nsl[tid];
+        dd[tid] = d;
+    }
+    if (s_total > 0) {
+        for (int r = 0; r < count; ++r) {
+            const int i = s_ord[r];
+            const int64_t K = s_key[i], R = s_rows[i];
+            const int n = s_nsl[i];
+            const int64_t E = s_E[i];
+            for (int j = tid; j < n; j += blockDim.x) {
+                Item it{};
+                it.row0 = (int64_t)j * R;
+                it.nrows = (int32_t)min(R, K - it.row0);
+                it.inst = i;
+                it.phase = 1;
+                it.slot_off = s_part0[i] + j * E;
+                items[s_pos1[i] + j] = it;
+            }
+            const int npf = s_npf[i];
+            const int64_t full = (int64_t)(n - 1) * npf;
+            for (int p = tid; p < s_pieces[i]; p += blockDim.x) {
+                const int j = p < full ? p / npf : n - 1;
+                const int64_t k = p < full ? p - (int64_t)j * npf : p - full;
+                const int64_t row0 = (int64_t)j * R, nr = min(R, K - row0);
+                const int64_t piece = update_piece(nr, s_f[i]);
+                Item it{};
+                it.row0 = row0 + k * piece;
+                it.nrows = (int32_t)min(piece, nr - k * piece);
+                it.inst = i;
+                it.phase = 2;
+                items[s_pos2[i] + p] = it;
+            }
+        }
+    }
+    if (tid == 0) {
+        ctrl->head = 0u;
+        ctrl->done = 0u;
+        ctrl->err = s_err;
+        ctrl->spin = spin;
+        ctrl->total = (unsigned)s_total;
+    }
+}
+
 }  // namespace
 
+// A plan owns a workspace laid out as above, filled once by the set-up
+// kernel, and a graph holding one launch of the persistent kernel.
 struct tsg_orth_plan_t {
     int dev = 0;
     int count = 0;
-    int total = 0;
     int grid = 0;
-    DevDesc* d_descs = nullptr;
-    Item* d_items = nullptr;
-    double* d_parts = nullptr;
-    unsigned* d_flags = nullptr;  // cnt[count], then ready[count]
-    Ctrl* d_ctrl = nullptr;
+    void* ws = nullptr;
+    tsg_orth_desc* d_in = nullptr;  // the caller's descriptors, uploaded
+    Layout L{};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
 namespace {
+
+template <class T>
+T* at(void* ws, size_t off)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
 
 void free_plan(tsg_orth_plan p)
 {
@@ -728,29 +966,74 @@ void free_plan(tsg_orth_plan p)
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->cap) hipStreamDestroy(p->cap);
-    hipFree(p->d_descs);
-    hipFree(p->d_items);
-    hipFree(p->d_parts);
-    hipFree(p->d_flags);
-    hipFree(p->d_ctrl);
+    hipFree(p->ws);
+    hipFree(p->d_in);
     if (switched) hipSetDevice(cur);
     delete p;
 }
 
-hipError_t launch(tsg_orth_plan p, hipStream_t s)
+// Resident blocks of the persistent kernel on the current device (0 on error).
+int64_t resident_blocks(int* dev_out)
 {
-    hipLaunchKernelGGL(orth_persistent, dim3(p->grid), dim3(kThreads), 0, s, p->d_descs, p->d_items, p->total,
-                       p->d_parts, p->d_flags, p->d_flags + p->count, p->d_ctrl, p->count);
+    int dev = 0, cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&orth_persistent),
+                                                         kThreads, 0);
+    if (e != hipSuccess || cus < 1) return 0;
+    if (dev_out) *dev_out = dev;
+    return (int64_t)cus * std::max(occ, 1);
+}
+
+hipError_t launch_setup(const tsg_orth_desc* d_in, int count, int64_t rows_fixed, int lag, int resident, void* ws,
+                        const Layout& L, hipStream_t s)
+{
+    hipLaunchKernelGGL(orth_setup, dim3(1), dim3(kMaxCount), 0, s, d_in, count, rows_fixed, lag, resident,
+                       kDefaultSpin, at<Ctrl>(ws, L.ctrl), at<DevDesc>(ws, L.descs), at<unsigned>(ws, L.flags),
+                       at<Item>(ws, L.items), L.max_items, L.max_parts);
     return hipGetLastError();
 }
 
-int64_t round16(int64_t x) { return (x + 15) / 16 * 16; }
+hipError_t launch_persistent(void* ws, const Layout& L, int count, int grid, hipStream_t s)
+{
+    unsigned* flags = at<unsigned>(ws, L.flags);
+    hipLaunchKernelGGL(orth_persistent, dim3(grid), dim3(kThreads), 0, s, at<DevDesc>(ws, L.descs),
+                       at<Item>(ws, L.items), at<double>(ws, L.parts), flags, flags + count, at<Ctrl>(ws, L.ctrl),
+                       count);
+    return hipGetLastError();
+}
+
+// Interleave lag of the queue (instances between an instance's slab items
+// and its updates); TSG_ORTH_LAG overrides it for tuning.
+int queue_lag(int count)
+{
+    const char* v = getenv("TSG_ORTH_LAG");
+    const int lag = v ? atoi(v) : kDefaultLag;
+    return lag < 1 ? count : std::min(lag, count);
+}
 
 tsg_status fail(tsg_status st, const char* fmt, long long a = 0, long long b = 0)
 {
     char buf[256];
     snprintf(buf, sizeof buf, fmt, a, b);
     return tsg::report(st, buf);
+}
+
+tsg_status read_error(Ctrl* d_ctrl)
+{
+    unsigned err = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&err, &d_ctrl->err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TSG_E_HIP, "device synchronisation failed");
+    if (!err) return TSG_OK;
+    const unsigned zero = 0;
+    if (hipMemcpy(&d_ctrl->err, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TSG_E_HIP, "could not clear the error word");
+    if (err & kErrDesc) return fail(TSG_E_ARG, "a descriptor failed the device-side checks: nothing was done");
+    if (err & kErrSpace)
+        return fail(TSG_E_NOMEM, "the batch does not fit the workspace (see tsg_workspace_size): nothing was done");
+    return fail(TSG_E_HIP, "an update waited past the spin limit: results invalid");
 }
 
 }  // namespace
@@ -764,6 +1047,8 @@ tsg_status tsg_orth_plan_create(tsg_orth_plan* plan, int32_t count, const tsg_or
     if (!plan) return fail(TSG_E_ARG, "plan is NULL");
     *plan = nullptr;
     if (!descs || count < 1) return fail(TSG_E_ARG, "need count >= 1 descriptors (count %lld)", count);
+    if (count > kMaxCount) return fail(TSG_E_UNSUPPORTED, "at most %lld instances per plan", kMaxCount);
+    int64_t slabs = 0, parts = 0;
     for (int i = 0; i < count; ++i) {
         const tsg_orth_desc& s = descs[i];
         if (s.K < 0 || s.M < 1 || s.N < 1) return fail(TSG_E_ARG, "instance %lld: K < 0, M < 1 or N < 1", i);
@@ -775,127 +1060,53 @@ tsg_status tsg_orth_plan_create(tsg_orth_plan* plan, int32_t count, const tsg_or
         if ((reinterpret_cast<uintptr_t>(s.V) | reinterpret_cast<uintptr_t>(s.W) |
              reinterpret_cast<uintptr_t>(s.C)) % sizeof(double))
             return fail(TSG_E_ARG, "instance %lld: pointer not aligned to 8 bytes", i);
-    }
-    // instances queued by decreasing input size (ties by index): the largest
-    // folds finish first and the last items of the queue are short
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return descs[a].K * (descs[a].M + descs[a].N) > descs[b].K * (descs[b].M + descs[b].N);
-    });
-    std::vector<DevDesc> dd(count);
-    std::vector<int64_t> rows(count);
-    int64_t part_total = 0;
-    for (int i = 0; i < count; ++i) {
-        const tsg_orth_desc& s = descs[i];
-        // byte offsets inside a slab (plus one step of rows past its end) stay below 2^31
-        const int64_t R_lim = (((int64_t)1 << 31) / (8 * std::max(s.ldv, s.ldw)) - 128) / 16 * 16;
-        int64_t R = rows_per_item;
-        if (R <= 0) {
-            R = std::max<int64_t>(16, round16(kItemBytes / (8 * (int64_t)(s.M + s.N))));
-            R = std::min(std::max(R, round16((s.K + kMaxSlabs - 1) / kMaxSlabs)), R_lim);
-        }
-        if (R < 1 || R > R_lim)
+        const int64_t R = slab_rows(s.K, s.M, s.N, s.ldv, s.ldw, rows_per_item);
+        if (R < 1)
             return fail(TSG_E_UNSUPPORTED, "instance %lld: slab height must be in [1, %lld] for its leading dimensions",
-                        i, R_lim);
-        rows[i] = R;
-        const int64_t nslab = s.K > 0 ? (s.K + R - 1) / R : 1;  // K = 0: one empty slab sets C = 0
+                        i, slab_limit(s.ldv, s.ldw));
+        const int64_t nslab = s.K > 0 ? (s.K + R - 1) / R : 1;
         if (nslab > ((int64_t)1 << 24)) return fail(TSG_E_UNSUPPORTED, "instance %lld: too many slabs", i);
-        DevDesc d{};
-        d.K = s.K;
-        d.V = s.V;
-        d.ldv = s.ldv;
-        d.W = s.W;
-        d.ldw = s.ldw;
-        d.C = s.C;
-        d.ldc = s.ldc;
-        d.M = s.M;
-        d.N = s.N;
-        d.part0 = part_total;
-        d.nparts = (int32_t)nslab;
-        part_total += nslab * (int64_t)s.M * s.N;
-        dd[i] = d;
+        slabs += nslab;
+        parts += nslab * s.M * s.N;
     }
-    int dev = 0, cus = 0, occ = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&orth_persistent),
-                                                         kThreads, 0);
-    if (e != hipSuccess || cus < 1) return fail(TSG_E_HIP, "no usable HIP device (%lld)", (long long)e);
-    const int64_t resident = (int64_t)cus * std::max(occ, 1);
-    std::vector<Item> items;
-    for (int i : order) {
-        const DevDesc& d = dd[i];
-        for (int64_t j = 0; j < d.nparts; ++j) {
-            Item it{};
-            it.row0 = j * rows[i];
-            it.nrows = (int32_t)std::min(rows[i], d.K - it.row0);
-            it.inst = i;
-            it.phase = 1;
-            it.slot_off = d.part0 + j * (int64_t)d.M * d.N;
-            items.push_back(it);
-        }
-    }
-    // Phase-2 items do not depend on one another, so with automatic sizing the
-    // end of the queue is cut finer: the last `resident` items cover a quarter
-    // of a slab each and the 2 * resident before them half a slab.  The blocks
-    // that run on alone after the queue has drained then hold short items.
-    // The queue is built back to front, then reversed.
-    std::vector<Item> upd;
-    for (auto o = order.rbegin(); o != order.rend(); ++o) {
-        const int i = *o;
-        const DevDesc& d = dd[i];
-        if (d.K == 0) continue;
-        for (int64_t j = d.nparts - 1; j >= 0; --j) {
-            const int64_t row0 = j * rows[i], nr = std::min(rows[i], d.K - row0);
-            const int64_t made = (int64_t)upd.size();
-            const int64_t f = rows_per_item > 0 ? 1 : made < resident ? 4 : made < 3 * resident ? 2 : 1;
-            const int64_t piece = f > 1 ? std::max<int64_t>(16, round16((nr + f - 1) / f)) : nr;
-            const int64_t np = (nr + piece - 1) / piece;
-            for (int64_t k = np - 1; k >= 0; --k) {
-                Item it{};
-                it.row0 = row0 + k * piece;
-                it.nrows = (int32_t)std::min(piece, nr - k * piece);
-                it.inst = i;
-                it.phase = 2;
-                upd.push_back(it);
-            }
-        }
-    }
-    items.insert(items.end(), upd.rbegin(), upd.rend());
-    if (items.size() > ((size_t)1 << 30)) return fail(TSG_E_UNSUPPORTED, "too many work items");
+    // at most four update pieces per slab
+    if (5 * slabs > ((int64_t)1 << 30)) return fail(TSG_E_UNSUPPORTED, "too many work items");
+    int dev = 0;
+    const int64_t resident = resident_blocks(&dev);
+    if (resident < 1) return fail(TSG_E_HIP, "no usable HIP device");
 
     tsg_orth_plan p = new (std::nothrow) tsg_orth_plan_t();
     if (!p) return fail(TSG_E_NOMEM, "host allocation failed");
     p->count = count;
-    p->total = (int)items.size();
     p->dev = dev;
-    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident, p->total));
-    const Ctrl ctrl0{0u, 0u, 0u, kDefaultSpin};
-    if (hipMalloc(&p->d_descs, sizeof(DevDesc) * count) != hipSuccess ||
-        hipMalloc(&p->d_items, sizeof(Item) * items.size()) != hipSuccess ||
-        hipMalloc(&p->d_parts, sizeof(double) * std::max<int64_t>(part_total, 1)) != hipSuccess ||
-        hipMalloc(&p->d_flags, sizeof(unsigned) * 2 * count) != hipSuccess ||
-        hipMalloc(&p->d_ctrl, sizeof(Ctrl)) != hipSuccess) {
+    p->grid = (int)resident;
+    p->L = make_layout(count, 5 * slabs, parts);
+    if (hipMalloc(&p->ws, p->L.bytes) != hipSuccess || hipMalloc(&p->d_in, sizeof(tsg_orth_desc) * count) != hipSuccess) {
         free_plan(p);
         return fail(TSG_E_NOMEM, "device allocation of the plan failed");
     }
-    if (hipMemcpy(p->d_descs, dd.data(), sizeof(DevDesc) * count, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(p->d_flags, 0, sizeof(unsigned) * 2 * count) != hipSuccess ||
-        hipMemcpy(p->d_ctrl, &ctrl0, sizeof(Ctrl), hipMemcpyHostToDevice) != hipSuccess ||
+    const Ctrl ctrl0{0u, 0u, 0u, kDefaultSpin, 0u, {0u, 0u, 0u}};
+    if (hipMemcpy(p->d_in, descs, sizeof(tsg_orth_desc) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(at<Ctrl>(p->ws, p->L.ctrl), &ctrl0, sizeof(Ctrl), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_setup(p->d_in, count, rows_per_item, queue_lag(count), (int)resident, p->ws, p->L, nullptr) !=
+            hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         free_plan(p);
         return fail(TSG_E_HIP, "upload of the plan failed");
     }
-    // one launch captured on a private stream; replays go to the caller's stream
+    const tsg_status st = read_error(at<Ctrl>(p->ws, p->L.ctrl));
+    if (st != TSG_OK) {
+        free_plan(p);
+        return st;
+    }
+    // one launch of the persistent kernel captured on a private stream;
+    // replays go to the caller's stream
     if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
         hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         free_plan(p);
         return fail(TSG_E_HIP, "stream capture could not start");
     }
-    e = launch(p, p->cap);
+    const hipError_t e = launch_persistent(p->ws, p->L, count, p->grid, p->cap);
     const hipError_t e2 = hipStreamEndCapture(p->cap, &p->graph);
     if (e != hipSuccess || e2 != hipSuccess ||
         hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -916,35 +1127,66 @@ tsg_status tsg_orth_plan_launch(tsg_orth_plan plan, void* stream)
 tsg_status tsg_orth_plan_run(tsg_orth_plan plan, void* stream)
 {
     if (!plan) return fail(TSG_E_ARG, "plan is NULL");
-    const hipError_t e = launch(plan, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_persistent(plan->ws, plan->L, plan->count, plan->grid, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? TSG_OK : fail(TSG_E_HIP, "kernel launch failed (%lld)", (long long)e);
 }
 
 tsg_status tsg_orth_plan_check(tsg_orth_plan plan)
 {
     if (!plan) return fail(TSG_E_ARG, "plan is NULL");
-    Ctrl c{};
-    if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&c, plan->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(TSG_E_HIP, "device synchronisation failed");
-    if (c.err) {
-        const unsigned zero = 0;
-        if (hipMemcpy(&plan->d_ctrl->err, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(TSG_E_HIP, "could not clear the error word");
-        return fail(TSG_E_HIP, "an update waited past the spin limit (%lld sleeps): results invalid", c.spin);
-    }
-    return TSG_OK;
+    return read_error(at<Ctrl>(plan->ws, plan->L.ctrl));
 }
 
 tsg_status tsg_orth_plan_set_spin_limit(tsg_orth_plan plan, uint32_t limit)
 {
     if (!plan) return fail(TSG_E_ARG, "plan is NULL");
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&plan->d_ctrl->spin, &limit, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(&at<Ctrl>(plan->ws, plan->L.ctrl)->spin, &limit, sizeof(unsigned), hipMemcpyHostToDevice) !=
+            hipSuccess)
         return fail(TSG_E_HIP, "could not set the spin limit");
     return TSG_OK;
 }
 
 void tsg_orth_plan_destroy(tsg_orth_plan plan) { free_plan(plan); }
 
+tsg_status tsg_orth_batched(const tsg_orth_desc* d_descs, int32_t count, void* workspace, size_t ws_bytes,
+                            void* stream)
+{
+    if (!d_descs || !workspace) return fail(TSG_E_ARG, "descriptors and workspace must not be NULL");
+    if (count < 1) return fail(TSG_E_ARG, "need count >= 1 descriptors (count %lld)", count);
+    if (count > kMaxCount) return fail(TSG_E_UNSUPPORTED, "at most %lld instances per call", kMaxCount);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 || reinterpret_cast<uintptr_t>(d_descs) % 8)
+        return fail(TSG_E_ARG, "workspace must be 256-byte and descriptors 8-byte aligned");
+    const Layout L0 = make_layout(count, kItemsPerInstance * count, 0);
+    if (ws_bytes < L0.bytes)
+        return fail(TSG_E_ARG, "workspace of %lld bytes is below the %lld this count needs", (long long)ws_bytes,
+                    (long long)L0.bytes);
+    const Layout L = make_layout(count, kItemsPerInstance * count, (int64_t)((ws_bytes - L0.parts) / sizeof(double)));
+    const int64_t resident = resident_blocks(nullptr);
+    if (resident < 1) return fail(TSG_E_HIP, "no usable HIP device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_setup(d_descs, count, 0, queue_lag(count), (int)resident, workspace, L, s);
+    if (e == hipSuccess) e = launch_persistent(workspace, L, count, (int)resident, s);
+    return e == hipSuccess ? TSG_OK : fail(TSG_E_HIP, "kernel launch failed (%lld)", (long long)e);
+}
+
+tsg_status tsg_orth_batched_check(void* workspace)
+{
+    if (!workspace) return fail(TSG_E_ARG, "workspace is NULL");
+    return read_error(at<Ctrl>(workspace, 0));
+}
+
 }  // extern "C"
+
+namespace tsg {
+// Workspace bytes of tsg_orth_batched for `count` instances none of which
+// exceeds K rows, M columns of V or N columns of W (contiguous rows; slabs as
+// tsg_orth_batched cuts them).  0 if the shape is outside the supported range.
+size_t orth_workspace_size(int64_t K, int32_t M, int32_t N, int32_t count)
+{
+    if (K < 0 || M < 1 || N < 1 || M > kMaxM || N > kMaxN || count < 1 || count > kMaxCount) return 0;
+    const int64_t R = slab_rows(K, M, N, M, N, 0);
+    const int64_t nslab = K > 0 && R > 0 ? (K + R - 1) / R : 1;
+    return make_layout(count, kItemsPerInstance * count, (int64_t)count * nslab * M * N).bytes;
+}
+}  // namespace tsg

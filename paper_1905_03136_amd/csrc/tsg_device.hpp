@@ -64,6 +64,16 @@ __device__ __forceinline__ zd ld_stream(const zf* p)
     return zd{(double)v.x, (double)v.y};
 }
 
+// Loads that keep binary32 values (the binary32-arithmetic kernels).
+__device__ __forceinline__ float ld_stream32(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ zf ld_stream32(const zf* p)
+{
+    const flt2 v = __builtin_nontemporal_load(reinterpret_cast<const flt2*>(p));
+    return zf{v.x, v.y};
+}
+__device__ __forceinline__ float keep(bool ok, float v) { return ok ? v : 0.0f; }
+__device__ __forceinline__ zf keep(bool ok, zf v) { return zf{ok ? v.re : 0.0f, ok ? v.im : 0.0f}; }
+
 // plain (cached) reads, e.g. of the old B when beta != 0
 __device__ __forceinline__ double ld_plain(const double* p) { return *p; }
 __device__ __forceinline__ double ld_plain(const float* p) { return (double)*p; }

@@ -1327,4 +1327,431 @@ tsmm_packed(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
 }
 
+// ============================================================================
+// Binary32 arithmetic (precision form with binary32 accumulation).
+//
+// A and B are stored in binary32 and the products are formed and summed by
+// v_mfma_f32_16x16x4f32 in binary32, at twice the matrix-core rate of the
+// binary64 products on gfx950.  Sums in binary32 run over short stretches
+// only: every RUN tiles (32 rows) the binary32 accumulators are added into
+// binary64 accumulators and cleared, so each binary32 sum holds at most 32
+// products, and every later addition (over the stretches, the waves, the
+// blocks) is binary64.  Error per entry: at most about (32 + 2) 2^-24 times
+// sum_k |a_k b_k|, against (K - 1) 2^-24 for one binary32 sum over all K
+// rows.  The output layout of the binary32 16x16x4 product differs from the
+// binary64 one: lane l, element r holds D(4 (l / 16) + r, l % 16) (checked
+// with an in-bounds probe on gfx950).
+// ============================================================================
+
+__device__ __forceinline__ flt4 mfma16f(float a, float b, flt4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ dbl4 widen_add(dbl4 acc, flt4 v)
+{
+    return dbl4{acc[0] + (double)v[0], acc[1] + (double)v[1], acc[2] + (double)v[2], acc[3] + (double)v[3]};
+}
+template <bool CPLX>
+using elem32_t = typename std::conditional<CPLX, zf, float>::type;
+__device__ __forceinline__ float lds_elem32(const float* p, int idx, float) { return p[idx]; }
+__device__ __forceinline__ zf lds_elem32(const float* p, int idx, zf) { return zf{p[2 * idx], p[2 * idx + 1]}; }
+
+// TSMTTSM in binary32 arithmetic: the blocked mapping of tsmttsm_mfma (MB x NB
+// blocks of 16 x 16 per wave, MW waves sharing a row group's rows, U groups of
+// four rows per tile, NBUF register sets in flight, optional slab reads FL),
+// with binary32 products and the binary64 flush every RUN tiles (4 U RUN = 32
+// rows per binary32 sum).  Complex data use four real products per block.
+template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1, int FL = 0>
+__global__ void __launch_bounds__(WPB * kWave, OCC)
+tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+            const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
+            double* __restrict__ ws, int conj)
+{
+    using T = elem32_t<CPLX>;
+    using S = T;  // storage = operand type
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int RG = WPB / MW;
+    constexpr int RT = 4 * U * RG;
+    constexpr int RUN = 8 / U;  // tiles per binary32 stretch: 4 U RUN = 32 rows
+    constexpr int EMAX = (MC ? MC : MW * MB * 16) * (NC ? NC : NB * 16) * CW;
+    static_assert(WPB % MW == 0 && 8 % U == 0, "waves split evenly; U divides 8");
+    static_assert(FL == 0 || (MW == 1 && MC > 0 && NC > 0 && (MC * CW) % FL == 0 && (NC * CW) % FL == 0),
+                  "slab reads: compile-time widths whose rows are multiples of FL, one wave per row group");
+    __shared__ double part[EMAX];
+
+    const S* __restrict__ A = static_cast<const S*>(Av);
+    const S* __restrict__ B = static_cast<const S*>(Bv);
+    const int M = MC ? MC : Mr;
+    const int N = NC ? NC : Nr;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int mw = wave % MW;
+    const int rg = wave / MW;
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+
+    // column offsets as in tsmttsm_mfma: lanes past the width read column 0
+    // of the same row; their products reach only entries that are not stored
+    int moff[MB], noff[NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int m = (mw * MB + i) * 16 + lc;
+        const bool ok = (MC && ((MW - 1) * MB + i + 1) * 16 <= MC) || m < M;
+        moff[i] = ok ? m : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int n = j * 16 + lc;
+        const bool ok = (NC && (j + 1) * 16 <= NC) || n < N;
+        noff[j] = ok ? n : 0;
+    }
+
+    dbl4 acc[MB][NB];                     // binary64 sums of the stretches
+    dbl4 acci[CPLX ? MB : 1][CPLX ? NB : 1];
+    flt4 s32[MB][NB];                     // binary32 sums of the current stretch
+    flt4 s32i[CPLX ? MB : 1][CPLX ? NB : 1];
+    const flt4 fz = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            s32[i][j] = fz;
+            if constexpr (CPLX) {
+                acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+                s32i[i][j] = fz;
+            }
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                acc[i][j] = widen_add(acc[i][j], s32[i][j]);
+                s32[i][j] = fz;
+                if constexpr (CPLX) {
+                    acci[i][j] = widen_add(acci[i][j], s32i[i][j]);
+                    s32i[i][j] = fz;
+                }
+            }
+    };
+
+    constexpr int SLA = FL ? 4 * U * MC * CW : 0, SLB = FL ? 4 * U * NC * CW : 0;  // real elements
+    constexpr int NLA = FL ? (SLA + kWave * FL - 1) / (kWave * FL) : 1;
+    constexpr int NLB = FL ? (SLB + kWave * FL - 1) / (kWave * FL) : 1;
+    using SV = typename slab_vec<float, FL ? FL : 1>::type;
+    __shared__ __attribute__((aligned(16))) float slab[FL ? WPB * (SLA + SLB) : 1];
+    float* const mya = slab + (FL ? wave * (SLA + SLB) : 0);
+    float* const myb = mya + SLA;
+
+    struct RowFrag {
+        T a[U][MB];
+        T b[U][NB];
+    };
+    struct SlabFrag {
+        SV a[NLA];
+        SV b[NLB];
+    };
+    using Frag = typename std::conditional<FL != 0, SlabFrag, RowFrag>::type;
+    Frag fr[NBUF];
+    auto load = [&](int64_t t, Frag& f) {
+        if constexpr (FL) {
+            const int64_t r0 = t * RT + (int64_t)rg * U * 4;
+            slab_load<FL, NLA>(reinterpret_cast<const float*>(A), r0 * MC * CW, K * (int64_t)(MC * CW), lane, f.a);
+            slab_load<FL, NLB>(reinterpret_cast<const float*>(B), r0 * NC * CW, K * (int64_t)(NC * CW), lane, f.b);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = t * RT + (int64_t)(rg * U + u) * 4 + lr;
+                const bool ok = row < K;
+                const int64_t rc = ok ? row : K - 1;
+#pragma unroll
+                for (int i = 0; i < MB; ++i) f.a[u][i] = keep(ok, ld_stream32(A + rc * lda + moff[i]));
+#pragma unroll
+                for (int j = 0; j < NB; ++j) f.b[u][j] = keep(ok, ld_stream32(B + rc * ldb + noff[j]));
+            }
+        }
+    };
+    int stretch = 0;
+    auto compute = [&](int64_t t, Frag& f) {
+        T av[U][MB], bv[U][NB];
+        if constexpr (FL) {
+            slab_put<FL, NLA, SLA>(mya, lane, f.a);
+            slab_put<FL, NLB, SLB>(myb, lane, f.b);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = t * RT + (int64_t)(rg * U + u) * 4 + lr < K;
+#pragma unroll
+                for (int i = 0; i < MB; ++i) av[u][i] = keep(ok, lds_elem32(mya, (4 * u + lr) * MC + moff[i], T{}));
+#pragma unroll
+                for (int j = 0; j < NB; ++j) bv[u][j] = keep(ok, lds_elem32(myb, (4 * u + lr) * NC + noff[j], T{}));
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i) av[u][i] = f.a[u][i];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) bv[u][j] = f.b[u][j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (!CPLX) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32[i][j] = mfma16f(av[u][i], bv[u][j], s32[i][j]);
+            } else {
+                // Re(a) products of every block first, then Im(a): dependent
+                // updates of one accumulator are 2 MB NB instructions apart
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        s32[i][j] = mfma16f(av[u][i].re, bv[u][j].re, s32[i][j]);
+                        s32i[i][j] = mfma16f(av[u][i].re, bv[u][j].im, s32i[i][j]);
+                    }
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    const float ai = conj ? -av[u][i].im : av[u][i].im;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        s32[i][j] = mfma16f(ai, -bv[u][j].im, s32[i][j]);
+                        s32i[i][j] = mfma16f(ai, bv[u][j].re, s32i[i][j]);
+                    }
+                }
+            }
+        }
+        if (++stretch == RUN) {
+            flush();
+            stretch = 0;
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
+    flush();
+
+    // row groups folded into the block partial one after the other
+    const int E = M * N * CW;
+    for (int g = 0; g < RG; ++g) {
+        if (rg == g) {
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = (mw * MB + i) * 16 + 4 * lr + r;
+                        const int n = j * 16 + lc;
+                        if (m < M && n < N) {
+                            const int e = (m * N + n) * CW;
+                            part[e] = (g == 0) ? acc[i][j][r] : part[e] + acc[i][j][r];
+                            if constexpr (CPLX) part[e + 1] = (g == 0) ? acci[i][j][r] : part[e + 1] + acci[i][j][r];
+                        }
+                    }
+        }
+        __syncthreads();
+    }
+    block_out<CW>(part, E, N, ws, C, ldc);
+}
+
+// TSMM in binary32 arithmetic: the mapping of tsmm_mfma (sixteen rows per
+// product chain, contraction over M in 4-wide slices, C staged once per block
+// in LDS in fragment order, U row blocks per tile), with C rounded to binary32
+// when it is staged and binary32 products summed by the matrix cores (at most
+// 64 products per output).  alpha, beta and the old B are applied in
+// binary64 and the result rounded once to binary32 when it is stored.
+template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, int FL = 0, bool RB = false>
+__global__ void __launch_bounds__(WPB * kWave)
+tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+         const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
+         double alpha, double beta, int conj, int opc)
+{
+    static_assert(FL == 0 || (!CPLX && MC > 0 && MC % FL == 0), "slab reads: real data, M a multiple of FL");
+    using T = elem32_t<CPLX>;
+    using S = T;
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int RT = 16 * U * WPB;
+    constexpr int NFRAG = MS * NB * kWave;
+    constexpr int SLAB = FL ? 16 * U * MC : 0;
+    constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
+    using SV = typename slab_vec<float, FL ? FL : 1>::type;
+    __shared__ float cf[NFRAG * CW];
+    __shared__ __attribute__((aligned(16))) float slab[FL ? WPB * SLAB : 1];
+
+    const S* __restrict__ A = static_cast<const S*>(Av);
+    S* __restrict__ B = static_cast<S*>(Bv);
+    const int M = MC ? MC : Mr;
+    const int N = NC ? NC : Nr;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+    const bool read_b = beta != 0.0;
+
+    // C in fragment order: cf[(s NB + j) 64 + l] = C(4 s + l/16, 16 j + l%16), binary32
+    for (int idx = threadIdx.x; idx < NFRAG; idx += blockDim.x) {
+        const int l = idx & (kWave - 1);
+        const int sj = idx / kWave;
+        const int s = sj / NB, j = sj - (sj / NB) * NB;
+        const int m = 4 * s + (l >> 4);
+        const int n = 16 * j + (l & 15);
+        const bool ok = m < M && n < N;
+        if constexpr (CPLX) {
+            const int64_t ci = small_index(m, n, ldc, opc);
+            cf[idx] = ok ? (float)Cm[2 * ci] : 0.0f;
+            cf[NFRAG + idx] = ok ? (float)(opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0f;
+        } else {
+            cf[idx] = ok ? (float)Cm[small_index(m, n, ldc, opc)] : 0.0f;
+        }
+    }
+    __syncthreads();
+
+    int koff[MS];
+    bool kok[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int m = 4 * s + lr;
+        kok[s] = (MC && 4 * s + 3 < MC) || m < M;
+        koff[s] = kok[s] ? m : 0;
+    }
+
+    using ARegs = typename std::conditional<FL != 0, slab_regs<SV, NL>, row_regs<T, U, MS>>::type;
+    struct Frag : ARegs {
+        T ob[RB ? U : 1][RB ? NB : 1][4];
+    };
+    Frag fr[NBUF];
+    const int64_t KM = K * (int64_t)M;
+    float* const mine = slab + (FL ? wave * SLAB : 0);
+    auto load = [&](int64_t t, Frag& f) {
+        if constexpr (RB) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + 4 * lr + r;
+                        const int n = 16 * j + lc;
+                        const int64_t rc = row < K ? row : K - 1;
+                        const int nc = n < N ? n : N - 1;
+                        f.ob[u][j][r] = ld_stream32(B + rc * ldb + nc);
+                    }
+        }
+        if constexpr (FL) {
+            const int64_t base = (t * RT + (int64_t)wave * U * 16) * MC;
+            slab_load<FL, NL>(reinterpret_cast<const float*>(A), base, KM, lane, f.v);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = t * RT + (int64_t)(wave * U + u) * 16 + lc;
+                const int64_t rc = row < K ? row : K - 1;
+#pragma unroll
+                for (int s = 0; s < MS; ++s) f.a[u][s] = keep(kok[s], ld_stream32(A + rc * lda + koff[s]));
+            }
+        }
+    };
+    auto compute = [&](int64_t t, Frag& f) {
+        __asm__ volatile("" ::: "memory");  // C operands stay in LDS (not hoisted into registers)
+        T av[U][MS];
+        if constexpr (FL) {
+            slab_put<FL, NL, SLAB>(mine, lane, f.v);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int s = 0; s < MS; ++s) av[u][s] = keep(kok[s], mine[(u * 16 + lc) * MC + koff[s]]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int s = 0; s < MS; ++s) av[u][s] = f.a[u][s];
+        }
+        flt4 acc[U][NB];
+        flt4 acci[CPLX ? U : 1][CPLX ? NB : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                acc[u][j] = flt4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (CPLX) acci[u][j] = flt4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            if constexpr (!CPLX) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float cr = cf[(s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16f(av[u][s], cr, acc[u][j]);
+                }
+            } else {
+                float cr[NB], ci[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    cr[j] = cf[(s * NB + j) * kWave + lane];
+                    ci[j] = cf[NFRAG + (s * NB + j) * kWave + lane];
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        acc[u][j] = mfma16f(av[u][s].re, cr[j], acc[u][j]);
+                        acci[u][j] = mfma16f(av[u][s].re, ci[j], acci[u][j]);
+                    }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const float ai = conj ? -av[u][s].im : av[u][s].im;
+                        acc[u][j] = mfma16f(ai, -ci[j], acc[u][j]);
+                        acci[u][j] = mfma16f(ai, cr[j], acci[u][j]);
+                    }
+            }
+        }
+        const bool full = (t + 1) * RT <= K;
+        // a lane stores four consecutive rows of one column; sixteen lanes
+        // cover 16 columns (64 bytes real, 128 complex) of each row
+        constexpr bool kStream = stream_rows(NC * (int)sizeof(S)) && (NB == 1 || 16 * sizeof(S) >= 128);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t rbase = t * RT + (int64_t)(wave * U + u) * 16 + 4 * lr;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int n = 16 * j + lc;
+                if ((NC && (NC % 16 == 0)) || n < N) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = rbase + r;
+                        if (full || row < K) {
+                            S* p = B + row * ldb + n;
+                            if constexpr (!CPLX) {
+                                double v = alpha * (double)acc[u][j][r];
+                                if constexpr (RB)
+                                    v = __builtin_fma(beta, (double)f.ob[u][j][r], v);
+                                else if (read_b)
+                                    v = __builtin_fma(beta, ld_plain(p), v);
+                                st_out<kStream>(p, v);
+                            } else {
+                                zd v = zd{alpha * (double)acc[u][j][r], alpha * (double)acci[u][j][r]};
+                                if (RB || read_b) {
+                                    zd o;
+                                    if constexpr (RB)
+                                        o = zd{(double)f.ob[u][j][r].re, (double)f.ob[u][j][r].im};
+                                    else
+                                        o = ld_plain(p);
+                                    v = zd{__builtin_fma(beta, o.re, v.re), __builtin_fma(beta, o.im, v.im)};
+                                }
+                                st_out<kStream>(p, v);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    pipeline<NBUF>(blockIdx.x, ntiles, (int64_t)gridDim.x, fr, load, compute);
+}
+
 }  // namespace tsg

@@ -90,6 +90,8 @@ constexpr int kMaxWidth = 64;
 }  // namespace
 
 namespace tsg {
+size_t orth_workspace_size(int64_t K, int32_t M, int32_t N, int32_t count);  // tsg_batched.hip
+
 // Error detail for tsg_last_error() from the library's other units.
 tsg_status report(tsg_status s, const char* msg)
 {
@@ -114,9 +116,10 @@ std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 std::map<std::pair<int, const tsg::Variant*>, int> g_occ;  // (device, variant) -> blocks per CU
+
 std::map<int, double*> g_scratch;  // device -> device address of its no-alloc scratch
 
-int is_complex(tsg_dtype dt) { return dt == TSG_C128 || dt == TSG_C64; }
+int is_complex(tsg_dtype dt) { return dt == TSG_C128 || dt == TSG_C64 || dt == TSG_C64_ACC32; }
 size_t elem_bytes(tsg_dtype dt)
 {
     switch (dt) {
@@ -124,8 +127,16 @@ size_t elem_bytes(tsg_dtype dt)
     case TSG_C128: return 16;
     case TSG_R32: return 4;
     case TSG_C64: return 8;
+    case TSG_R32_ACC32: return 4;
+    case TSG_C64_ACC32: return 8;
     }
     return 0;
+}
+// Binary64-arithmetic type whose kernels also serve a binary32-arithmetic
+// type (they are at least as accurate); -1 for the other types.
+int twin_of(tsg_dtype dt)
+{
+    return dt == TSG_R32_ACC32 ? (int)TSG_R32 : dt == TSG_C64_ACC32 ? (int)TSG_C64 : -1;
 }
 
 tsg_status device_info(int dev, DeviceInfo* out)
@@ -188,8 +199,25 @@ tsg_status scratch_of(int dev, double** out)
 
 // Choose the variant: the exact (op, dtype, M, N) one if its access
 // requirements hold, else the first run-time-width variant covering (M, N).
+const tsg::Variant* pick_for(int op, int dt, int M, int N, const void* A, int64_t lda, const void* X,
+                             int64_t ldx, bool beta_nz);
+
+// The variant of (op, dt): for a binary32-arithmetic type, its own exact-width
+// variant if there is one, else what its binary64-arithmetic twin would run.
 const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int64_t lda, const void* X,
                          int64_t ldx, bool beta_nz = false)
+{
+    const tsg::Variant* v = pick_for(op, (int)dt, M, N, A, lda, X, ldx, beta_nz);
+    const int twin = twin_of(dt);
+    if (twin >= 0 && (!v || v->M == 0)) {
+        const tsg::Variant* w = pick_for(op, twin, M, N, A, lda, X, ldx, beta_nz);
+        if (w) return w;
+    }
+    return v;
+}
+
+const tsg::Variant* pick_for(int op, int dt, int M, int N, const void* A, int64_t lda, const void* X,
+                             int64_t ldx, bool beta_nz)
 {
     const bool a_pairs = (lda % 2 == 0) && aligned(A, 16);
     const bool x_pairs = (ldx % 2 == 0) && aligned(X, 16);
@@ -201,7 +229,7 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
             const tsg::Variant& v = tsg::kVariants[i];
             if (g_force != v.name) continue;
             const bool serves = (v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN);
-            if (v.op == op && v.dt == (int)dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs) &&
+            if (v.op == op && v.dt == dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs) &&
                 (!v.flatA || rows_contiguous) && (!v.readB || beta_nz))
                 return &v;
         }
@@ -209,7 +237,7 @@ const tsg::Variant* pick(int op, tsg_dtype dt, int M, int N, const void* A, int6
     }
     for (int i = 0; i < tsg::kNumVariants; ++i) {
         const tsg::Variant& v = tsg::kVariants[i];
-        if (v.op != op || v.dt != (int)dt) continue;
+        if (v.op != op || v.dt != dt) continue;
         if (v.pairA && !a_pairs) continue;
         if (v.pairX && !x_pairs) continue;
         if (v.flatA && !rows_contiguous) continue;
@@ -255,8 +283,7 @@ tsg_status get_workspace(int dev, hipStream_t stream, size_t bytes, Workspace** 
 tsg_status validate(tsg_dtype dt, int64_t K, int32_t M, int32_t N, const void* A, int64_t lda, const void* X,
                     int64_t ldx, const void* Y, int64_t ldy, int op)
 {
-    if (dt != TSG_R64 && dt != TSG_C128 && dt != TSG_R32 && dt != TSG_C64)
-        return fail(TSG_E_ARG, "unknown dtype %d", (int)dt);
+    if (elem_bytes(dt) == 0) return fail(TSG_E_ARG, "unknown dtype %d", (int)dt);
     if (K < 0) return fail(TSG_E_ARG, "K = %lld < 0", (long long)K);
     if (M < 1 || N < 1) return fail(TSG_E_ARG, "M = %d, N = %d: widths must be >= 1", M, N);
     if (M > kMaxWidth || N > kMaxWidth)
@@ -430,8 +457,11 @@ tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N
     return tsg_tsmm_op(dt, conjA, TSG_OP_N, K, M, N, A, lda, C, ldc, B, ldb, alpha, beta, stream);
 }
 
-size_t tsg_workspace_size(tsg_dtype dt, int64_t K, int32_t M, int32_t N)
+size_t tsg_workspace_size(int32_t op_kind, tsg_dtype dt, int64_t K, int32_t M, int32_t N, int32_t count)
 {
+    if (op_kind == TSG_KIND_TSMM) return 0;
+    if (op_kind == TSG_KIND_ORTH) return dt == TSG_R64 ? tsg::orth_workspace_size(K, M, N, count) : 0;
+    if (op_kind != TSG_KIND_TSMTTSM) return 0;
     if (M < 1 || N < 1 || M > kMaxWidth || N > kMaxWidth || K < 0) return 0;
     int dev;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

@@ -11,9 +11,12 @@ split of C), already pruned by a register model.
 
 ``run`` times each candidate at K rows (default 2^24), rotating through
 enough disjoint buffer sets that consecutive calls never find their data in
-the 256 MB Infinity Cache, and checks that every candidate reproduces the
-first candidate's result bit for bit on integer-valued inputs (exact in
-binary64, so all correct mappings agree).  Records are appended to a JSONL
+the 256 MB Infinity Cache.  Before it is timed, every candidate must equal the
+exact product of integer-valued inputs, computed on the host in int64
+arithmetic (the inputs' products and sums are exact in binary64, and in the
+binary32-arithmetic kernels' 32-row stretches), bit for bit, both on the full
+grid and on a grid of three blocks (every block then works through many
+tiles); a candidate that differs is recorded as failed and never chosen.  Records are appended to a JSONL
 database, so an interrupted run resumes where it stopped; ``tuned.json``
 keeps the fastest correct configuration per (operation, dtype, M, N) and is
 read by the code generator when the product library is built.
@@ -55,6 +58,21 @@ def cmd_build(args):
     variants = [v for v in variants if v["M"] == 0 or
                 ((not ops or v["op"] in ops) and (not dtypes or v["dt"] in dtypes))]
     build.build(variants=variants, lib_path=TUNE_LIB, tag="_tune")
+
+
+def exact_product(op, A, B):
+    """op(A)^T B ("tsmttsm") or A B ("tsmm") of integer-valued numpy arrays in
+    int64 arithmetic (complex: the real expansion), returned as float64 or
+    complex128.  Independent of the oracle and of the library."""
+    import numpy as np
+    mul = (lambda x, y: x.T @ y) if op == "tsmttsm" else (lambda x, y: x @ y)
+    if not np.iscomplexobj(A):
+        return mul(A.astype(np.int64), B.astype(np.int64)).astype(np.float64)
+    ar, ai = A.real.astype(np.int64), A.imag.astype(np.int64)
+    br, bi = B.real.astype(np.int64), B.imag.astype(np.int64)
+    re = mul(ar, br) - mul(ai, bi)
+    im = mul(ar, bi) + mul(ai, br)
+    return re.astype(np.float64) + 1j * im.astype(np.float64)
 
 
 def _algorithmic(op, cplx, K, M, N, real_bytes=8):
@@ -105,20 +123,23 @@ def cmd_run(args):
         op, dt, M, N = key
         if (dtypes and dt not in dtypes) or (ops and op not in ops):
             continue
-        cplx = dt in ("c128", "c64")
+        cplx = codegen.DTYPES[dt][1]
         f32 = codegen.is_f32(dt)
         cw = 2 if cplx else 1
         tdt = torch.complex128 if cplx else torch.float64            # small matrix C
-        sdt = {"r64": torch.float64, "c128": torch.complex128,
-               "r32": torch.float32, "c64": torch.complex64}[dt]      # storage of A, B
+        sdt = (torch.complex64 if cplx else torch.float32) if f32 else tdt  # storage of A, B
         cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
         if not cands:
             continue
-        # integer-valued reference problem (exact in binary64): all candidates must agree bit for bit
+        # integer-valued problem: every candidate must give the exact product
         kc = 4099
-        Ai = torch.from_numpy(inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)).to(dev).to(sdt)
-        Bi = torch.from_numpy(inputs.host_integers(kc, N, 7, inputs.STREAM_B, cplx)).to(dev).to(sdt)
-        Xi = torch.from_numpy(inputs.host_integers(M, N, 7, inputs.STREAM_C, cplx)).to(dev)
+        Ah = inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)
+        Bh = inputs.host_integers(kc, N, 7, inputs.STREAM_B, cplx)
+        Xh = inputs.host_integers(M, N, 7, inputs.STREAM_C, cplx)
+        exact = torch.from_numpy(exact_product(op, Ah, Bh if op == "tsmttsm" else Xh)).to(dev)
+        Ai = torch.from_numpy(Ah).to(dev).to(sdt)
+        Bi = torch.from_numpy(Bh).to(dev).to(sdt)
+        Xi = torch.from_numpy(Xh).to(dev)
         # buffer sets for timing (pool reinterpreted as binary32 for the precision form)
         pool = pools[cplx].view(torch.float32) if f32 else pools[cplx]
         ws_elems = K * (M + N) * cw
@@ -139,7 +160,6 @@ def cmd_run(args):
         Xs = inputs.device_uniform(M, N, 3, inputs.STREAM_C, cplx, dev)
         Cout = torch.empty((M, N), dtype=tdt, device=dev)
         byts, flops = _algorithmic(op, cplx, K, M, N, 4 if f32 else 8)
-        ref = None
         for v in cands:
             name = codegen.variant_name(v)
             rec = dict(op=op, dt=dt, M=M, N=N, name=name, cfg=v["cfg"], K=K)
@@ -149,15 +169,19 @@ def cmd_run(args):
                 continue
             _lib.check(_lib.tsg_force_variant(name))
             try:
+                acc = "f32" if codegen.is_a32(dt) else "f64"
                 if op == "tsmttsm":
-                    res = api.tsmttsm(Ai, Bi).clone()
-                    call = (lambda s: api.tsmttsm(s[0], s[1], out=Cout))
+                    once = lambda: api.tsmttsm(Ai, Bi, acc=acc).clone()
+                    call = (lambda s: api.tsmttsm(s[0], s[1], out=Cout, acc=acc))
                 else:
-                    res = api.tsmm(Ai, Xi).clone()
-                    call = (lambda s: api.tsmm(s[0], Xs, out=s[1]))
-                if ref is None:
-                    ref = res
-                ok = bool(torch.equal(res, ref))
+                    once = lambda: api.tsmm(Ai, Xi, acc=acc).to(exact.dtype)
+                    call = (lambda s: api.tsmm(s[0], Xs, out=s[1], acc=acc))
+                ok = bool(torch.equal(once(), exact))
+                _lib.check(_lib.tsg_set_grid_limit(3))
+                try:
+                    ok = ok and bool(torch.equal(once(), exact))
+                finally:
+                    _lib.tsg_set_grid_limit(0)
                 for w in range(args.warmup):
                     call(sets[w % R])
                 evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -190,8 +214,19 @@ def write_table(db_path, out_path, merge=None):
     """Fastest correct configuration per (op, dtype, M, N) from the database;
     entries of an existing table ``merge`` that the database does not cover
     are kept."""
-    from paper_1905_03136_amd.codegen import needs_layout
+    from paper_1905_03136_amd.codegen import A32_TWIN, needs_layout
     best, plain = {}, {}
+    # binary32-arithmetic (op, dtype, M, N) that the database timed: only those
+    # get an entry (built from their own and their twin's records)
+    seen_a32 = set()
+    with open(db_path) as f:
+        for line in f:
+            try:
+                r = json.loads(line)
+            except ValueError:
+                continue
+            if r.get("dt") in A32_TWIN:
+                seen_a32.add((r["op"], r["dt"], r["M"], r["N"]))
     if merge and os.path.exists(merge):
         with open(merge) as f:
             for e in json.load(f).get("entries", []):
@@ -207,12 +242,18 @@ def write_table(db_path, out_path, merge=None):
                 continue
             if not r.get("ok") or "us" not in r:
                 continue
-            key = (r["op"], r["dt"], r["M"], r["N"])
-            if key not in best or best[key].get("_kept") or r["us"] < best[key]["us"]:
-                best[key] = r
-            # fastest configuration without layout requirements on A
-            if not needs_layout(r["cfg"]) and (key not in plain or plain[key].get("_kept") or r["us"] < plain[key]["us"]):
-                plain[key] = r
+            keys = [(r["op"], r["dt"], r["M"], r["N"])]
+            # a binary64-arithmetic kernel also serves its binary32-arithmetic twin type
+            keys += [(r["op"], a, r["M"], r["N"]) for a, t in A32_TWIN.items() if t == r["dt"]]
+            for key in keys:
+                if key[1] != r["dt"] and key not in seen_a32:
+                    continue
+                if key not in best or best[key].get("_kept") or r["us"] < best[key]["us"]:
+                    best[key] = r
+                # fastest configuration without layout requirements on A
+                if not needs_layout(r["cfg"]) and (key not in plain or plain[key].get("_kept") or
+                                                   r["us"] < plain[key]["us"]):
+                    plain[key] = r
     entries = []
     for k, r in sorted(best.items(), key=lambda kv: (kv[0][0], kv[0][1], kv[0][2] * kv[0][3])):
         e = dict(op=k[0], dt=k[1], M=k[2], N=k[3], cfg=r["cfg"], name=r["name"], us=r["us"],
@@ -239,6 +280,7 @@ _DIMENSIONS = {
 
 
 def ablation(db_paths, ops=None):
+    from paper_1905_03136_amd.codegen import DTYPES
     """Cost of fixing one design dimension, from autotuner databases: for each
     (op, dtype, M, N) and each value v of a dimension, the fastest correct
     configuration with that value, as a slowdown over the fastest overall;
@@ -268,7 +310,7 @@ def ablation(db_paths, ops=None):
             if len(by) < 2:
                 continue
             for v, t in by.items():
-                out.setdefault((op, dt[0] if dt in ("r64", "r32") else "z", dim, v), []).append(t / best)
+                out.setdefault((op, "z" if DTYPES[dt][1] else "r", dim, v), []).append(t / best)
     rows = []
     for (op, kind, dim, v), xs in sorted(out.items(), key=lambda kv: [str(x) for x in kv[0]]):
         gm = math.exp(sum(math.log(x) for x in xs) / len(xs))
@@ -290,10 +332,10 @@ def main(argv=None):
     b = sub.add_parser("build")
     b.add_argument("--widths", default="graded")
     b.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
-    b.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")
+    b.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
-    r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64")
+    r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
     r.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
     r.add_argument("--K", type=int, default=1 << 24)
     r.add_argument("--db", default="gpurun_out/tune_db.jsonl")

@@ -27,7 +27,7 @@ def lib():
 def test_header_declares_expected_api():
     syms = declared_symbols()
     for s in ("tsg_tsmttsm", "tsg_tsmm", "tsg_init", "tsg_finalize", "tsg_status_string", "tsg_last_error",
-              "tsg_workspace_size", "tsg_reserve", "tsg_kernel_name"):
+              "tsg_workspace_size", "tsg_reserve", "tsg_kernel_name", "tsg_orth_batched", "tsg_orth_batched_check"):
         assert s in syms
 
 
@@ -88,7 +88,7 @@ def test_no_device_reports_hip_error(lib):
         pytest.skip("a GPU is present")
     assert _lib.tsg_tsmttsm(0, 0, 100, 4, 4, A, 4, A, 4, A, 4, None) == _lib.TSG_E_HIP
     assert _lib.tsg_init(0) == _lib.TSG_E_HIP
-    assert _lib.tsg_workspace_size(0, 1 << 20, 4, 4) == 0
+    assert _lib.tsg_workspace_size(_lib.TSG_KIND_TSMTTSM, 0, 1 << 20, 4, 4, 1) == 0
 
 
 def test_kernel_names_cover_all_widths(lib):
@@ -166,3 +166,30 @@ def test_orth_plan_no_device(lib):
         pytest.skip("a GPU is present")
     st, plan = _lib.tsg_orth_plan_create([_desc(), _desc(K=0)], 0, None)
     assert st == _lib.TSG_E_HIP and plan is None
+
+
+def test_orth_workspace_size_bounds_the_batch(lib):
+    """The batched call's workspace size needs no device: it grows with the
+    widths and the instance count and is 0 outside the supported range."""
+    ws = lambda K, M, N, c: _lib.tsg_workspace_size(_lib.TSG_KIND_ORTH, _lib.TSG_R64, K, M, N, c)
+    assert ws(1 << 22, 64, 16, 64) > 0
+    assert ws(1 << 22, 64, 16, 64) > ws(1 << 22, 8, 4, 64)
+    assert ws(1 << 22, 64, 16, 128) > ws(1 << 22, 64, 16, 64)
+    # slabs of at most 256 per instance: the partial sums of 64 instances of 64 x 16
+    assert ws(1 << 22, 64, 16, 64) >= 64 * 256 * 64 * 16 * 8
+    assert ws(1 << 22, 65, 16, 64) == 0 and ws(1 << 22, 64, 17, 64) == 0
+    assert ws(1 << 22, 64, 16, 0) == 0 and ws(1 << 22, 64, 16, 1025) == 0
+    assert _lib.tsg_workspace_size(_lib.TSG_KIND_ORTH, _lib.TSG_C128, 1 << 20, 4, 4, 4) == 0
+    assert _lib.tsg_workspace_size(_lib.TSG_KIND_TSMM, _lib.TSG_R64, 1 << 20, 4, 4, 1) == 0
+
+
+def test_orth_batched_host_validation(lib):
+    A = 1 << 12
+    n = _lib.tsg_workspace_size(_lib.TSG_KIND_ORTH, _lib.TSG_R64, 1000, 8, 8, 2)
+    assert _lib.tsg_orth_batched(None, 2, A, n, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_orth_batched(A, 2, None, n, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_orth_batched(A, 0, A, n, None) == _lib.TSG_E_ARG
+    assert _lib.tsg_orth_batched(A, 1025, A, n, None) == _lib.TSG_E_UNSUPPORTED
+    assert _lib.tsg_orth_batched(A + 8, 2, A + 8, n, None) == _lib.TSG_E_ARG   # workspace not 256-aligned
+    assert _lib.tsg_orth_batched(A, 2, A, 64, None) == _lib.TSG_E_ARG          # below the queue's own size
+    assert _lib.tsg_orth_batched_check(None) == _lib.TSG_E_ARG

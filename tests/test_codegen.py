@@ -14,10 +14,13 @@ def test_emission_is_deterministic(tmp_path):
 
 
 def test_every_width_pair_is_served():
+    """Every (M, N) has a run-time-width variant; the binary32-arithmetic types
+    use their binary64-arithmetic twin's (the runtime falls back to them)."""
     v = codegen.all_variants()
     for op in codegen.OPS:
         for dt in codegen.DTYPES:
-            gens = [x for x in v if x["op"] == op and x["dt"] == dt and x["M"] == 0]
+            served = codegen.A32_TWIN.get(dt, dt)
+            gens = [x for x in v if x["op"] == op and x["dt"] == served and x["M"] == 0]
             for M, N in itertools.product(range(1, 65), repeat=2):
                 assert any(M <= g["maxM"] and N <= g["maxN"] for g in gens), (op, dt, M, N)
 
@@ -53,3 +56,19 @@ def test_default_configs_respect_register_budget():
                     assert w * w * cw + 2 * c["U"] * 2 * w * cw <= 100
                 if c["kind"] == "mfma" and op == "tsmttsm":
                     assert c["MB"] * c["NB"] * 4 * cw <= 64
+
+
+def test_binary32_arithmetic_candidates_and_defaults():
+    """r32a / c64a: their own binary32-product kernels plus every candidate of
+    the binary64-arithmetic twin; the tuning library holds only their own."""
+    for op in codegen.OPS:
+        for dt, twin in codegen.A32_TWIN.items():
+            for M, N in ((32, 32), (64, 64), (8, 32)):
+                c = codegen.candidates(op, dt, M, N)
+                own = [x for x in c if x["kind"] == "a32"]
+                assert own and len(c) == len(own) + len(codegen.candidates(op, twin, M, N))
+                assert codegen.default_config(op, dt, M, N)["kind"] == "a32"
+    tv = codegen.tuning_variants([(32, 32)])
+    assert all(x["cfg"]["kind"] == "a32" for x in tv if x["M"] and codegen.is_a32(x["dt"]))
+    names = {codegen.variant_name(x) for x in tv}
+    assert "tsmttsm_r32a_32x32_a32_b2x2w1_u2" in names

@@ -228,3 +228,127 @@ def test_orth_full_size_sampled():
         ref_rows = oracle.tsmm_rows(V[rows], C, W0[i][rows], alpha=-1.0, beta=1.0)
         check_bound(Wn, ref_rows, np.abs(W0[i][rows]) + np.abs(V[rows]) @ np.abs(C), what="rows %d" % i)
     plan.close()
+
+
+# ------------------------------------------------ descriptors in device memory
+def test_orth_batched_device_descriptors_match_plan():
+    """tsg_orth_batched (descriptors in device memory, queue built by the
+    set-up kernel on every call) gives the plan's results bit for bit (same
+    slabs, same summation orders) and meets the oracle's bounds; a second
+    call on the same workspace does too."""
+    print("orth device descriptors", flush=True)
+    host_inst = _instances(SHAPES, 38)
+    pairs_a = [(dev(V), dev(W)) for V, W in host_inst]
+    pairs_b = [(dev(V), dev(W)) for V, W in host_inst]
+    plan = api.OrthPlan(pairs_a)
+    try:
+        plan.launch()
+        plan.check()
+    finally:
+        plan.close()
+    batch = api.OrthBatch(pairs_b)
+    batch.run()
+    batch.check()
+    for i in range(len(host_inst)):
+        assert torch.equal(batch.C[i], plan.C[i]), "instance %d: C differs from the plan's" % i
+        assert torch.equal(pairs_b[i][1], pairs_a[i][1]), "instance %d: W differs from the plan's" % i
+    for i, ((V, W0), (_, dW), dC) in enumerate(zip(host_inst, pairs_b, batch.C)):
+        check_instance(V, W0, host(dC), host(dW), "instance %d" % i)
+    # again on the same workspace, from the original W
+    for (_, w), (_, w0) in zip(pairs_b, host_inst):
+        w.copy_(dev(w0))
+    batch.run()
+    batch.check()
+    for i in range(len(host_inst)):
+        assert torch.equal(batch.C[i], plan.C[i]) and torch.equal(pairs_b[i][1], pairs_a[i][1]), i
+
+
+def test_orth_batched_integer_exact_device_descriptors():
+    print("orth device descriptors integer", flush=True)
+    host_inst = _instances(SHAPES, 39, integer=True)
+    pairs = [(dev(V), dev(W)) for V, W in host_inst]
+    batch = api.OrthBatch(pairs)
+    batch.run()
+    batch.check()
+    for i, ((V, W0), (_, dW), dC) in enumerate(zip(host_inst, pairs, batch.C)):
+        C_ref = oracle.tsmttsm(V, W0)
+        assert np.array_equal(host(dC), C_ref), i
+        assert np.array_equal(host(dW), oracle.tsmm(V, C_ref, W0.copy(), alpha=-1.0, beta=1.0)), i
+
+
+def test_orth_batched_captured_graph_replays():
+    """The call captured by the caller into a graph: every replay (with eager
+    work restoring W and synchronisations between) equals the eager call bit
+    for bit."""
+    print("orth device descriptors graph", flush=True)
+    host_inst = _instances(SHAPES[:10], 40)
+    pairs = [(dev(V), dev(W)) for V, W in host_inst]
+    W0 = [w.clone() for _, w in pairs]
+    batch = api.OrthBatch(pairs)
+    batch.run()
+    batch.check()
+    ref_C = [c.clone() for c in batch.C]
+    ref_W = [w.clone() for _, w in pairs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            batch.run()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for (_, w), w0 in zip(pairs, W0):
+            w.copy_(w0)
+        for c in batch.C:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        batch.check()
+        for i in range(len(pairs)):
+            assert torch.equal(batch.C[i], ref_C[i]), "replay %d instance %d" % (rep, i)
+            assert torch.equal(pairs[i][1], ref_W[i]), "replay %d instance %d" % (rep, i)
+    for i, ((V, w0), dC, dW) in enumerate(zip(host_inst, ref_C, ref_W)):
+        check_instance(V, w0, host(dC), host(dW), "instance %d" % i)
+
+
+def test_orth_batched_device_side_rejections():
+    """Errors the host cannot see (the descriptors are in device memory) are
+    found by the set-up kernel: nothing runs, every C and W is left as it
+    was, and the check reports the cause; the next valid call works."""
+    print("orth device descriptors rejections", flush=True)
+    host_inst = _instances(SHAPES[:4], 41)
+    pairs = [(dev(V), dev(W)) for V, W in host_inst]
+    batch = api.OrthBatch(pairs)
+    W0 = [w.clone() for _, w in pairs]
+    for c in batch.C:
+        c.fill_(7.0)
+    # an invalid width written into the device copy of descriptor 2 (M = 65)
+    good = batch.d_descs.clone()
+    desc_size = batch.d_descs.numel() // len(pairs)
+    bad = host(batch.d_descs).copy()
+    bad[2 * desc_size + 8:2 * desc_size + 12] = np.frombuffer(np.int32(65).tobytes(), dtype=np.uint8)
+    batch.d_descs.copy_(dev(bad))
+    batch.run()
+    with pytest.raises(_lib.TsgError) as e:
+        batch.check()
+    assert e.value.status == _lib.TSG_E_ARG
+    for (_, w), w0, c in zip(pairs, W0, batch.C):
+        assert torch.equal(w, w0) and bool(torch.all(c == 7.0))
+    batch.check()                                           # the report was cleared
+    # a workspace too small for the partial sums (but large enough for the queue)
+    batch.d_descs.copy_(good)
+    full = batch.workspace
+    small = _lib.tsg_workspace_size(_lib.TSG_KIND_ORTH, _lib.TSG_R64, 1, 1, 1, len(pairs))  # queue, no room
+    batch.workspace = full[:small]
+    batch.run()
+    with pytest.raises(_lib.TsgError) as e:
+        batch.check()
+    assert e.value.status == _lib.TSG_E_NOMEM
+    for (_, w), w0 in zip(pairs, W0):
+        assert torch.equal(w, w0)
+    batch.workspace = full
+    batch.run()
+    batch.check()
+    for i, ((V, W0h), (_, dW), dC) in enumerate(zip(host_inst, pairs, batch.C)):
+        check_instance(V, W0h, host(dC), host(dW), "instance %d" % i)
