@@ -161,6 +161,45 @@ def test_tsmm_error_bound_vs_exact(oracle_mod):
             assert abs(Fraction(B[k, n]) - ex) <= Fraction(gamma(M) * absum)
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tsmm_compensated_error_bound_vs_exact(oracle_mod, cplx):
+    """The compensated (Dot2) TSMM against exact rationals on rows that
+    cancel: column 0 of A is large (1e8 scale) and column M-1 is its exact
+    negative, with equal rows 0 and M-1 of C, so the large products cancel
+    only at the last term of each sum.  The plain recursive sum loses the
+    small terms' low bits to the large partial sum (error about u 1e8), while
+    Dot2 must stay within u |exact| + gamma_n^2 sum |a c| (Ogita, Rump and
+    Oishi 2005, Proposition 4.5), n the number of products per sum."""
+    K, M, N = 48, 6, 3
+    A = inputs.host_uniform(K, M, 7, inputs.STREAM_A, cplx)
+    C = inputs.host_uniform(M, N, 7, inputs.STREAM_C, cplx)
+    A[:, 0] *= 1e8
+    A[:, M - 1] = -A[:, 0]
+    C[M - 1] = C[0]
+    Bp = oracle_mod.tsmm(A, C)
+    Bc = oracle_mod.tsmm(A, C, compensated=True)
+    plain_excess = 0
+    for k in range(K):
+        for n in range(N):
+            if not cplx:
+                ex = _frac_dot_real(A[k], C[:, n])
+                absum = float(np.sum(np.abs(A[k] * C[:, n])))
+                assert abs(Fraction(Bc[k, n]) - ex) <= Fraction(U * abs(float(ex)) + gamma(M) ** 2 * absum)
+                plain_excess += abs(Fraction(Bp[k, n]) - ex) > Fraction(U * abs(float(ex)) + gamma(M) ** 2 * absum)
+            else:
+                er, ei = _frac_dot_cplx(A[k], C[:, n])
+                x, y = A[k], C[:, n]
+                sr = float(np.sum(np.abs(x.real * y.real)) + np.sum(np.abs(x.imag * y.imag)))
+                si = float(np.sum(np.abs(x.real * y.imag)) + np.sum(np.abs(x.imag * y.real)))
+                br = Fraction(U * abs(float(er)) + gamma(2 * M) ** 2 * sr)
+                bi = Fraction(U * abs(float(ei)) + gamma(2 * M) ** 2 * si)
+                assert abs(Fraction(Bc[k, n].real) - er) <= br
+                assert abs(Fraction(Bc[k, n].imag) - ei) <= bi
+                plain_excess += (abs(Fraction(Bp[k, n].real) - er) > br) + (abs(Fraction(Bp[k, n].imag) - ei) > bi)
+    # the case has teeth: the plain sum misses the compensated bound
+    assert plain_excess > 0
+
+
 # ------------------------------------------------------------- closed forms
 @pytest.mark.parametrize("cplx", [False, True])
 def test_closed_forms(oracle_mod, cplx):

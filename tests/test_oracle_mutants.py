@@ -29,6 +29,9 @@ MUTANTS = {
     "tsmm_imag_sign": ("si = si + (ar * xi + ai * xr);", "si = si + (ar * xi - ai * xr);"),
     "lost_compensation": ("*c = *c + (et + ep);", "*c = *c + 0.0 * (et + ep);"),
     "alpha_dropped": ("brow[2 * n]     = alpha * sr;", "brow[2 * n]     = sr;"),
+    "tsmm_lost_compensation": ("if (comp) s = s + c;", "if (comp) s = s + 0.0 * c;"),
+    "tsmm_cplx_lost_compensation": ("if (comp) { sr = sr + cr; si = si + ci; }",
+                                    "if (comp) { sr = sr + 0.0 * cr; si = si + ci; }"),
 }
 
 PIN_TESTS = [
@@ -43,6 +46,7 @@ PIN_TESTS = [
     (pins.test_complex_equals_real_expansion, [dict(conj=False), dict(conj=True)]),
     (pins.test_leading_dimensions_and_beta_zero, [dict(cplx=False), dict(cplx=True)]),
     (pins.test_numpy_blas_agreement, [dict(M=4, N=4, cplx=True)]),
+    (pins.test_tsmm_compensated_error_bound_vs_exact, [dict(cplx=False), dict(cplx=True)]),
 ]
 
 
