@@ -32,7 +32,12 @@
  *    the stream is being captured into a graph is impossible and returns
  *    TSG_E_CAPTURE; call the operation once outside capture (or tsg_reserve)
  *    first.  Calls that run concurrently on different streams use different
- *    workspaces; calls on one stream are ordered by the stream.
+ *    workspaces; calls on one stream are ordered by the stream.  A workspace
+ *    that a later call outgrows is retired, not freed, until tsg_finalize(),
+ *    so a graph that captured it stays valid.  A captured TSMTTSM writes its
+ *    partial sums into the capture stream's workspace whichever stream the
+ *    graph is replayed on: replays must not overlap in time with calls on
+ *    the capture stream or with replays of other graphs captured there.
  *  - No C++ exception crosses this interface.  tsg_last_error() gives a
  *    thread-local text for the last non-OK status of the calling thread.
  */

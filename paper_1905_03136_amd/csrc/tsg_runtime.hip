@@ -115,6 +115,9 @@ struct Workspace {
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+// Outgrown workspaces, kept until tsg_finalize: a graph captured earlier on
+// the stream may still hold one of them and write its partial sums there.
+std::vector<std::pair<int, void*>> g_retired;
 std::map<std::pair<int, const tsg::Variant*>, int> g_occ;  // (device, variant) -> blocks per CU
 
 std::map<int, double*> g_scratch;  // device -> device address of its no-alloc scratch
@@ -265,16 +268,13 @@ tsg_status get_workspace(int dev, hipStream_t stream, size_t bytes, Workspace** 
         return fail(TSG_E_CAPTURE, "workspace must grow to %zu bytes while the stream is captured; "
                                    "run the call once before capture or use tsg_reserve", bytes);
     hipError_t e;
-    if (w.data) {
-        e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return fail(TSG_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-        hipFree(w.data);
-        w.data = nullptr;
-        w.bytes = 0;
-    }
-    size_t grow = bytes < (1u << 20) ? (1u << 20) : bytes;
-    e = hipMalloc(&w.data, grow);
+    // the outgrown buffer is retired, not freed (see g_retired)
+    const size_t grow = bytes < (1u << 20) ? (1u << 20) : bytes;
+    void* fresh = nullptr;
+    e = hipMalloc(&fresh, grow);
     if (e != hipSuccess) return fail(TSG_E_NOMEM, "hipMalloc(%zu): %s", grow, hipGetErrorString(e));
+    if (w.data) g_retired.emplace_back(dev, w.data);
+    w.data = fresh;
     w.bytes = grow;
     *out = &w;
     return TSG_OK;
@@ -526,6 +526,11 @@ void tsg_finalize(void)
         if (kv.second.data) hipFree(kv.second.data);
     }
     g_ws.clear();
+    for (auto& r : g_retired) {
+        hipSetDevice(r.first);
+        hipFree(r.second);
+    }
+    g_retired.clear();
     g_occ.clear();
     if (cur >= 0) hipSetDevice(cur);
 }
