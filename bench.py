@@ -6,9 +6,15 @@ One step is one pass of the plain width sweep: TSMTTSM (C = A^T B) and TSMM
 36 calls on inputs already resident in HBM (seeded uniform(-1, 1) data,
 generated on the device).  The value is the sweep's algorithmic bytes per
 second (Eq. 1 of the paper: every element of A, B and C moves once); the JSON
-line also carries each call's GB/s, GFLOP/s and fraction of the
-min(HBM, FP64) roofline, the roofline record of the dominant kernel and the
-CPU oracle timed on a bounded sample of the same sweep.
+line also carries each call's median / min / max time over the timed steps,
+GB/s, GFLOP/s and fraction of the min(HBM, FP64) roofline, the roofline
+record of the dominant kernel, the measured FP64 rates of the chip, clocks
+and power, and the CPU oracle timed on the same sweep.  After the timed
+steps (unless --no-forms) come the production forms and the other workload
+sizes: the precision form (binary32 storage, binary64 and binary32
+arithmetic, K = 2^25, with errors per result), the batched
+orthogonalisation, the small-K product (K = 2^20, M = N = 4) and the
+autograd form (K = 2^22, M = N = 32).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --all-widths      # every square width 1..64 instead (one JSON line each)
@@ -72,8 +78,9 @@ def measure_bs(torch, src, dst, nbytes=8 << 30, reps=5):
     return out
 
 
-def time_call(torch, fn, reps=3, warmup=1):
-    """Median device time of fn() over `reps` runs (events on the current stream)."""
+def time_stats(torch, fn, reps=5, warmup=1):
+    """Median, minimum and maximum device time (s) of fn() over `reps` runs
+    (events on the current stream)."""
     for _ in range(warmup):
         fn()
     ts = []
@@ -84,48 +91,172 @@ def time_call(torch, fn, reps=3, warmup=1):
         e1.record()
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3)
-    return sorted(ts)[len(ts) // 2]
+    ts.sort()
+    return {"median": ts[len(ts) // 2], "min": ts[0], "max": ts[-1]}
 
 
-def precision_form(torch, api, inputs, dev, K=1 << 25, widths=(8, 32, 64)):
-    """Speedup of binary32 storage (exact products, binary64 accumulation)
-    over binary64 storage for both products, real and complex, at K = 2^25."""
+def time_call(torch, fn, reps=3, warmup=1):
+    """Median device time of fn() over `reps` runs (events on the current stream)."""
+    return time_stats(torch, fn, reps, warmup)["median"]
+
+
+def _host(t):
+    """Device tensor -> numpy array in extended precision (values exact)."""
+    import numpy as np
+    x = t.detach().cpu().numpy()
+    return x.astype(np.clongdouble if np.iscomplexobj(x) else np.longdouble)
+
+
+def _exact_entries(torch, A, B, entries, conj=False):
+    """Entries (m, n) of op(A)^T B from the stored values, computed on the
+    host: every product of two values is formed and summed in 80-bit extended
+    precision (products of binary32 values are exact there; a pairwise sum of
+    K <= 2^25 terms errs by at most about 25 * 2^-64 relative to sum |a b|),
+    i.e. a reference far more accurate than either arithmetic it judges.
+    Returns (values, sum |a| |b|) per entry."""
+    import numpy as np
+    cols = {}
+    vals, absb = [], []
+    for m, n in entries:
+        if ("a", m) not in cols:
+            cols["a", m] = _host(A[:, m])
+        if ("b", n) not in cols:
+            cols["b", n] = _host(B[:, n])
+        a, b = cols["a", m], cols["b", n]
+        if conj:
+            a = np.conj(a)
+        vals.append(np.sum(a * b))
+        absb.append(np.sum(np.abs(a) * np.abs(b)))
+    return np.array(vals), np.array(absb)
+
+
+def _exact_rows(torch, A, C, rows):
+    """Rows of A C from the stored values, in extended precision (see
+    _exact_entries); returns (rows of A C, rows of |A| |C|)."""
+    import numpy as np
+    idx = torch.as_tensor(rows, device=A.device)
+    a = _host(A.index_select(0, idx))
+    c = _host(C)
+    return (a[:, :, None] * c[None, :, :]).sum(axis=1), (np.abs(a)[:, :, None] * np.abs(c)[None, :, :]).sum(axis=1)
+
+
+def _errors(got, ref, absb):
+    """Normwise and elementwise relative errors and the cancellation-free
+    measure max |got - ref| / (|a|^T |b|) over the sampled entries."""
+    import numpy as np
+    got = np.asarray(got).astype(ref.dtype)
+    d = np.abs(got - ref)
+    return {"normwise": float(np.sqrt(np.sum(d ** 2)) / np.sqrt(np.sum(np.abs(ref) ** 2))),
+            "max_elementwise": float(np.max(d / np.maximum(np.abs(ref), 1e-300))),
+            "max_vs_abs_products": float(np.max(d / np.maximum(absb, 1e-300)))}
+
+
+# the storage / arithmetic forms of the precision bench: (name, storage, arithmetic)
+PREC_FORMS = [("fp64", "binary64", "binary64"), ("fp32_acc64", "binary32", "binary64"),
+              ("fp32_acc32", "binary32", "binary32")]
+
+
+def precision_form(torch, api, inputs, dev, K=1 << 25, widths=(8, 32, 64), nrows=64):
+    """The precision form against binary64 storage at K = 2^25, real and
+    complex, M = N in `widths`, both products: binary32 / complex64 storage
+    of the tall operands with binary64 arithmetic (values widened exactly,
+    products exact, binary64 sums) and with binary32 arithmetic (binary32
+    products on the matrix cores summed in binary32 over 32-row stretches,
+    binary64 beyond and across blocks).  Per result: time, speedup over
+    binary64 storage, and the error on sampled outputs (TSMTTSM: entries
+    (0, 0), (w-1, w/2), (w/2, w-1); TSMM: `nrows` rows spread over K) against
+    the exact result of the stored values ("arithmetic") and of the binary64
+    data before storage rounding ("end to end"), for uniform(-1, 1) data and
+    for the ill-conditioned case: near-parallel columns base + 1e-4 noise_j,
+    TSMTTSM as the Gram matrix A^T A, TSMM with a small matrix whose columns
+    sum to zero (so that A C cancels by about 1e4)."""
+    import numpy as np
     out = []
     for cplx in (False, True):
         t64 = torch.complex128 if cplx else torch.float64
         t32 = torch.complex64 if cplx else torch.float32
-        A = inputs.device_uniform(K, 64, 7, inputs.STREAM_A, cplx, dev)
-        B = inputs.device_uniform(K, 64, 7, inputs.STREAM_B, cplx, dev)
-        A32, B32 = A.to(t32), B.to(t32)
-        X = inputs.device_uniform(64, 64, 7, inputs.STREAM_C, cplx, dev)
+        sz = 16 if cplx else 8
         for w in widths:
-            a64 = A.reshape(-1)[:K * w].view(K, w)
-            b64 = B.reshape(-1)[:K * w].view(K, w)
-            a32 = A32.reshape(-1)[:K * w].view(K, w)
-            b32 = B32.reshape(-1)[:K * w].view(K, w)
-            x = X[:w, :w].contiguous()
             rec = {"dtype": "Z" if cplx else "D", "M": w, "N": w, "K": K}
-            for op in ("tsmttsm", "tsmm"):
-                if op == "tsmttsm":
-                    f64 = (lambda: api.tsmttsm(a64, b64))
-                    f32 = (lambda: api.tsmttsm(a32, b32))
+            entries = sorted({(0, 0), (w - 1, w // 2), (w // 2, w - 1)})
+            rows = [int(r) for r in np.linspace(0, K - 1, nrows).round()]
+            for case in ("uniform", "ill_conditioned"):
+                if case == "uniform":
+                    A = inputs.device_uniform(K, w, 7 + w, inputs.STREAM_A, cplx, dev)
+                    B = inputs.device_uniform(K, w, 7 + w, inputs.STREAM_B, cplx, dev)
+                    X = inputs.device_uniform(w, w, 7 + w, inputs.STREAM_C, cplx, dev)
                 else:
-                    f64 = (lambda: api.tsmm(a64, x, out=b64))
-                    f32 = (lambda: api.tsmm(a32, x, out=b32))
-                t_64 = time_call(torch, f64)
-                t_32 = time_call(torch, f32)
-                s = 16 if cplx else 8
-                rec[op] = {"us_fp64": round(t_64 * 1e6, 1), "us_fp32": round(t_32 * 1e6, 1),
-                           "speedup": round(t_64 / t_32, 3),
-                           "GBps_fp32": round((s // 2) * K * 2 * w / t_32 / 1e9, 1),
-                           "kernel_fp32": api.kernel_name(op, t32, w, w)}
+                    base = inputs.device_uniform(K, 1, 7 + w, inputs.STREAM_BASE, cplx, dev)
+                    A = inputs.device_uniform(K, w, 7 + w, inputs.STREAM_NOISE0, cplx, dev)
+                    A.mul_(1e-4).add_(base)
+                    del base
+                    B = A
+                    X = torch.from_numpy(inputs.zero_column_sum(w, w, 7 + w, inputs.STREAM_C, cplx)).to(dev)
+                A32 = A.to(t32)
+                B32 = A32 if B is A else B.to(t32)
+                Bout = torch.empty((K, w), dtype=t64, device=dev)
+                Bout32 = torch.empty((K, w), dtype=t32, device=dev)
+                # exact references: of the stored binary32 values, and of the binary64 data
+                ref32, ab32 = _exact_entries(torch, A32, B32, entries)
+                ref64, ab64 = _exact_entries(torch, A, B, entries)
+                rref32, rab32 = _exact_rows(torch, A32, X, rows)
+                rref64, rab64 = _exact_rows(torch, A, X, rows)
+                res = {}
+                for op in ("tsmttsm", "tsmm"):
+                    r = {}
+                    for name, storage, arith in PREC_FORMS:
+                        a, b = (A, B) if storage == "binary64" else (A32, B32)
+                        acc = "f32" if arith == "binary32" else "f64"
+                        if op == "tsmttsm":
+                            Cout = torch.empty((w, w), dtype=t64, device=dev)
+                            fn = (lambda a=a, b=b, acc=acc, Cout=Cout: api.tsmttsm(a, b, out=Cout, acc=acc))
+                        else:
+                            o = Bout if storage == "binary64" else Bout32
+                            fn = (lambda a=a, acc=acc, o=o: api.tsmm(a, X, out=o, acc=acc))
+                        st = time_stats(torch, fn, reps=5, warmup=1) if case == "uniform" else None
+                        fn()
+                        torch.cuda.synchronize()
+                        if op == "tsmttsm":
+                            got = np.array([Cout[m, n].item() for m, n in entries])
+                            e_ar = _errors(got, ref32 if storage == "binary32" else ref64,
+                                           ab32 if storage == "binary32" else ab64)
+                            e_ee = _errors(got, ref64, ab64)
+                        else:
+                            o = Bout if storage == "binary64" else Bout32
+                            got = o.index_select(0, torch.as_tensor(rows, device=dev)).cpu().numpy()
+                            e_ar = _errors(got, rref32 if storage == "binary32" else rref64,
+                                           rab32 if storage == "binary32" else rab64)
+                            e_ee = _errors(got, rref64, rab64)
+                        item = {"error_arithmetic": e_ar, "error_end_to_end": e_ee,
+                                "kernel": api.kernel_name(op, t64 if storage == "binary64" else t32, w, w, acc=acc)}
+                        if st:
+                            byts = (sz if storage == "binary64" else sz // 2) * K * 2 * w + sz * w * w
+                            item.update(us=round(st["median"] * 1e6, 1), us_min=round(st["min"] * 1e6, 1),
+                                        us_max=round(st["max"] * 1e6, 1), GBps=round(byts / st["median"] / 1e9, 1))
+                        r[name] = item
+                    if case == "uniform":
+                        for name, _, _ in PREC_FORMS[1:]:
+                            r[name]["speedup_vs_fp64"] = round(r["fp64"]["us"] / r[name]["us"], 3)
+                    res[op] = r
+                rec[case] = res
+                del A, B, A32, B32, Bout, Bout32, X
+                torch.cuda.empty_cache()
             out.append(rec)
-        del A, B, A32, B32
-        torch.cuda.empty_cache()
-    return {"note": "binary32 / complex64 storage of A and B (values widened exactly, products exact, "
-                    "binary64 accumulation and reduction) against binary64 / complex128 storage; arithmetic "
-                    "error against the binary64 oracle on the stored values is at the binary64 level "
-                    "(tests check <= 1e-12 for TSMTTSM, one binary32 rounding for TSMM outputs)",
+            print("[bench] precision form %s %dx%d: speedup TSMTTSM %.2f / %.2f, TSMM %.2f / %.2f "
+                  "(binary64 / binary32 arithmetic)" % (
+                      rec["dtype"], w, w, rec["uniform"]["tsmttsm"]["fp32_acc64"]["speedup_vs_fp64"],
+                      rec["uniform"]["tsmttsm"]["fp32_acc32"]["speedup_vs_fp64"],
+                      rec["uniform"]["tsmm"]["fp32_acc64"]["speedup_vs_fp64"],
+                      rec["uniform"]["tsmm"]["fp32_acc32"]["speedup_vs_fp64"]), file=sys.stderr, flush=True)
+    return {"note": "fp64: binary64 / complex128 storage; fp32_acc64: binary32 / complex64 storage, values "
+                    "widened exactly, binary64 products and sums; fp32_acc32: binary32 storage, binary32 "
+                    "products summed in binary32 over 32-row stretches (TSMM: over the M terms of one "
+                    "output), binary64 beyond and across blocks.  error_arithmetic is against the exact result "
+                    "of the stored values, error_end_to_end against the exact result of the binary64 data "
+                    "before it was rounded to binary32 (both formed on the host in 80-bit extended "
+                    "precision), on sampled outputs: TSMTTSM entries (0,0), (w-1,w/2), (w/2,w-1); TSMM 64 "
+                    "rows spread over K.  ill_conditioned: columns base + 1e-4 noise_j; TSMTTSM computes the "
+                    "Gram matrix A^T A, TSMM multiplies by a small matrix with zero column sums",
             "widths": out}
 
 
@@ -160,6 +291,19 @@ def batched_form(torch, api, inputs, dev, reps=5):
     plan = api.OrthPlan(pairs)
     t_persist = time_call(torch, plan.launch, reps=reps, warmup=2)
     plan.check()
+    # the same step through tsg_orth_batched (descriptors in device memory,
+    # the queue built on the device by a set-up kernel, then the same
+    # persistent kernel), direct and captured in a graph
+    ob = api.OrthBatch(pairs)
+    t_batched = time_call(torch, ob.run, reps=reps, warmup=2)
+    ob.check()
+    sb = torch.cuda.Stream()
+    sb.wait_stream(torch.cuda.current_stream())
+    gb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gb, stream=sb):
+        ob.run()
+    t_batched_graph = time_call(torch, gb.replay, reps=reps, warmup=2)
+    ob.check()
     t_sep = time_call(torch, separate, reps=reps, warmup=2)
     # the separate calls captured into one graph (workspaces reserved by the warm-up on the capture stream)
     s = torch.cuda.Stream()
@@ -185,10 +329,11 @@ def batched_form(torch, api, inputs, dev, reps=5):
     rel_C = max(float((a - b).norm() / b.norm().clamp_min(1e-300)) for a, b in zip(C_p, Cs))
     rel_W = max(float((a - w).norm() / w.norm().clamp_min(1e-300)) for a, (_, w) in zip(W_p, pairs))
     plan.close()
-    del g
+    del g, gb, ob
     return {"instances": 64, "rows": sum(k for k, _, _ in shapes),
             "algorithmic_bytes": byts, "cache_ideal_bytes": ideal, "flops": flops,
             "us_persistent_graph": round(t_persist * 1e6, 1), "us_128_launches": round(t_sep * 1e6, 1),
+            "us_orth_batched": round(t_batched * 1e6, 1), "us_orth_batched_graph": round(t_batched_graph * 1e6, 1),
             "us_128_launches_graph": round(t_graph * 1e6, 1),
             "speedup_vs_launches": round(t_sep / t_persist, 3),
             "speedup_vs_launch_graph": round(t_graph / t_persist, 3),
@@ -202,7 +347,120 @@ def batched_form(torch, api, inputs, dev, reps=5):
                     "separate-launch results from the same inputs"}
 
 
+def small_k_leg(torch, api, inputs, dev, K=1 << 20, M=4, N=4, sets=20, reps=5):
+    """TSMTTSM, real, K = 2^20 rows, M = N = 4 (67 MB per call, inside the
+    256 MB Infinity Cache): `sets` distinct operand pairs (1.3 GB in all) are
+    used in turn so that no call finds its operands in the cache, as a
+    caller's stream of independent small products would.  Median, minimum
+    and maximum per-call time over reps passes over the sets."""
+    pairs = [(inputs.device_uniform(K, M, 50 + i, inputs.STREAM_A, False, dev),
+              inputs.device_uniform(K, N, 50 + i, inputs.STREAM_B, False, dev)) for i in range(sets)]
+    C = torch.empty((M, N), dtype=torch.float64, device=dev)
+    for a, b in pairs:
+        api.tsmttsm(a, b, out=C)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        evs = []
+        for a, b in pairs:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.tsmttsm(a, b, out=C)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ts += [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+    ts.sort()
+    t = ts[len(ts) // 2]
+    byts, flops = algorithmic("tsmttsm", False, K, M, N)
+    del pairs
+    return {"workload": "TSMTTSM D K=2^20 M=N=4, %d operand sets rotated (%.2f GB)" % (sets, sets * 8 * K * (M + N) / 1e9),
+            "us": round(t * 1e6, 2), "us_min": round(ts[0] * 1e6, 2), "us_max": round(ts[-1] * 1e6, 2),
+            "GBps": round(byts / t / 1e9, 1), "roof_frac": round(roofline_time(byts, flops) / t, 4),
+            "kernel": api.kernel_name("tsmttsm", torch.float64, M, N), "calls_timed": len(ts)}
+
+
+def autograd_leg(torch, inputs, dev, K=1 << 22, w=32, reps=5):
+    """The differentiation form at K = 2^22, M = N = 32, real and complex:
+    forward C = A^T B through autograd.TSMTTSM, backward dA = B dC^T,
+    dB = A dC (complex: the conjugate forms) on the TSMM kernels, dC uniform.
+    Algorithmic bytes: forward s K (M + N) + s M N; backward two TSMMs,
+    2 s K (M + N) + 2 s M N."""
+    from paper_1905_03136_amd import autograd
+    out = []
+    for cplx in (False, True):
+        A = inputs.device_uniform(K, w, 9, inputs.STREAM_A, cplx, dev).requires_grad_(True)
+        B = inputs.device_uniform(K, w, 9, inputs.STREAM_B, cplx, dev).requires_grad_(True)
+        dC = inputs.device_uniform(w, w, 9, inputs.STREAM_DC, cplx, dev)
+        holder = {}
+
+        def fwd():
+            holder["C"] = autograd.tsmttsm(A, B)
+
+        def bwd():
+            A.grad = B.grad = None
+            holder["C"].backward(dC, retain_graph=True)
+
+        tf = time_stats(torch, fwd, reps=reps, warmup=1)
+        fwd()
+        tb = time_stats(torch, bwd, reps=reps, warmup=1)
+        s = 16 if cplx else 8
+        fb = s * K * 2 * w + s * w * w
+        bb = 2 * s * K * 2 * w + 2 * s * w * w
+        ff = (8 if cplx else 2) * w * w * K
+        out.append({"dtype": "Z" if cplx else "D", "K": K, "M": w, "N": w,
+                    "forward_us": round(tf["median"] * 1e6, 1), "backward_us": round(tb["median"] * 1e6, 1),
+                    "forward_GBps": round(fb / tf["median"] / 1e9, 1), "backward_GBps": round(bb / tb["median"] / 1e9, 1),
+                    "forward_roof_frac": round(roofline_time(fb, ff) / tf["median"], 4),
+                    "backward_roof_frac": round(roofline_time(bb, 2 * ff) / tb["median"], 4)})
+        del A, B, dC, holder
+        torch.cuda.empty_cache()
+    return out
+
+
+def fp64_peaks(torch, occs=(1, 2, 4, 8), iters=20000):
+    """Measured FP64 rates of the chip (the paper computes its own peak,
+    Section 1.6): register-only loops of the library's peak probes with eight
+    independent matrix-core (or sixteen vector FMA) chains per lane, the best
+    over blocks of 256 threads per CU; and the binary32 matrix-core rate."""
+    from paper_1905_03136_amd import _lib
+    s = torch.cuda.current_stream().cuda_stream
+    kinds = {"mfma_f64": _lib.TSG_PEAK_MFMA_F64, "valu_f64": _lib.TSG_PEAK_VALU_F64,
+             "mixed_f64": _lib.TSG_PEAK_MIXED_F64, "mfma_f32": _lib.TSG_PEAK_MFMA_F32}
+    out = {}
+    for name, kind in kinds.items():
+        per = {}
+        for occ in occs:
+            fl = [0.0]
+
+            def run():
+                st, fl[0] = _lib.tsg_peak_probe(kind, occ, iters, s)
+                _lib.check(st)
+            per[str(occ)] = round(fl[0] / time_call(torch, run, reps=3) / 1e12, 2)
+        out[name] = {"TFLOPs_by_blocks_per_cu": per, "best_TFLOPs": max(per.values())}
+    return out
+
+
+def gpu_state():
+    """Clocks and power as rocm-smi reports them (None where it is missing)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], stdout=subprocess.PIPE,
+                           stderr=subprocess.DEVNULL, text=True, timeout=30)
+        d = json.loads(r.stdout)
+        card = d[sorted(d)[0]]
+        keep = {k: v for k, v in card.items() if "clk" in k.lower() or "power" in k.lower()}
+        return keep or None
+    except Exception:
+        return None
+
+
 def cpu_baseline(K_sample):
+    """The oracle as it stands, timed on the host over the bench step's 36
+    calls at K_sample rows.  It splits the independent output rows over its
+    threads (rows of C for TSMTTSM: at most M threads; rows of B for TSMM:
+    all of them), so `cores` is the time-weighted mean of the threads the
+    calls actually kept busy; the per-call counts are listed too."""
     import numpy as np
 
     import oracle
@@ -211,6 +469,8 @@ def cpu_baseline(K_sample):
     threads = oracle.max_threads()
     total_bytes = 0
     t_total = 0.0
+    busy = 0.0
+    per = []
     for cplx in (False, True):
         A = inputs.host_uniform(K_sample, 64, 0, inputs.STREAM_A, cplx)
         B = inputs.host_uniform(K_sample, 64, 0, inputs.STREAM_B, cplx)
@@ -219,18 +479,27 @@ def cpu_baseline(K_sample):
             a = np.ascontiguousarray(A[:, :M])
             b = np.ascontiguousarray(B[:, :N])
             X = np.ascontiguousarray(Xfull[:M, :N])
-            t0 = time.perf_counter()
-            oracle.tsmttsm(a, b)
-            t1 = time.perf_counter()
-            oracle.tsmm(a, X)
-            t2 = time.perf_counter()
-            t_total += t2 - t0
             for op in ("tsmttsm", "tsmm"):
+                t0 = time.perf_counter()
+                if op == "tsmttsm":
+                    oracle.tsmttsm(a, b)
+                else:
+                    oracle.tsmm(a, X)
+                dt = time.perf_counter() - t0
+                used = min(M, threads) if op == "tsmttsm" else threads
+                t_total += dt
+                busy += used * dt
                 total_bytes += algorithmic(op, cplx, K_sample, M, N)[0]
-    return {"value": total_bytes / t_total / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "the same 36-call sweep (TSMTTSM+TSMM, D and Z, 9 widths) at K=%d rows instead of "
-                      "2^24; plain binary64 triple loop, threads over output rows; %.1f s" % (K_sample, t_total),
-            "seconds": t_total, "cpu": platform.processor() or platform.machine()}
+                per.append({"op": op, "dtype": "Z" if cplx else "D", "M": M, "N": N, "s": round(dt, 3),
+                            "threads": used})
+            del a, b
+        del A, B
+    return {"value": total_bytes / t_total / 1e9, "unit": "GB/s", "cores": round(busy / t_total, 2),
+            "kind": "oracle",
+            "sample": "the bench step's 36 calls (TSMTTSM+TSMM, D and Z, 9 widths) at K=%d rows; plain "
+                      "binary64 triple loop, threads over output rows; %.1f s" % (K_sample, t_total),
+            "host_threads": threads, "seconds": t_total, "calls": per,
+            "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
 
 
 def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False):
@@ -284,10 +553,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    # 3 * 2^22 rows: the 36 calls of the sweep move 201 GB at that K, about 13 s
-    # of oracle work on 16 host threads (15.4 GB/s measured at 2^23 rows);
-    # inputs of at most 12.9 GB per matrix
-    ap.add_argument("--cpu-sample", type=int, default=3 << 22, help="rows of the oracle sample (0 = skip)")
+    # 2^24 rows, the bench's own K: the 36 calls move 268 GB, about 17 s of
+    # oracle work on 16 host threads (15.4 GB/s measured at 2^23 rows);
+    # host inputs of at most 17.2 GB per matrix
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="rows of the oracle sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
     ap.add_argument("--all-widths", action="store_true",
@@ -356,6 +625,7 @@ def main():
           % (bs["read"] / 1e9, bs["copy"] / 1e9, a.steps), file=sys.stderr, flush=True)
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
            for _ in range(a.steps)]
+    gpu_before = gpu_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
@@ -363,32 +633,44 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
+    gpu_after = gpu_state()
     per = []
     for i, c in enumerate(calls):
-        ms = sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(a.steps)) / a.steps
-        t = ms * 1e-3
+        ts = sorted(evs[s][i][0].elapsed_time(evs[s][i][1]) * 1e-3 for s in range(a.steps))
+        t = ts[len(ts) // 2]
         rt = roofline_time(c["bytes"], c["flops"])
         rt_bs = roofline_time(c["bytes"], c["flops"], bw=bs["read"] if c["op"] == "tsmttsm" else bs["copy"])
         per.append(dict(op=c["op"], dtype="Z" if c["cplx"] else "D", M=c["M"], N=c["N"], kernel=c["kernel"],
-                        us=round(ms * 1e3, 2), GBps=round(c["bytes"] / t / 1e9, 1),
+                        us=round(t * 1e6, 2), us_min=round(ts[0] * 1e6, 2), us_max=round(ts[-1] * 1e6, 2),
+                        GBps=round(c["bytes"] / t / 1e9, 1),
                         GFLOPs=round(c["flops"] / t / 1e9, 1), roof_frac=round(rt / t, 4),
                         roof_frac_bs=round(rt_bs / t, 4),
                         bound="fp64" if c["flops"] / FP64_PEAK > c["bytes"] / HBM_PEAK else "hbm"))
+    peaks = fp64_peaks(torch)
     dom_i = max(range(len(per)), key=lambda i: per[i]["us"])
     d = per[dom_i]
     dc = calls[dom_i]
     dt = d["us"] * 1e-6
+    # a complex kernel in the three-product (Gauss) form executes 6MNK of the
+    # 8MNK algorithmic flops on the matrix cores
+    g3 = dc["cplx"] and "_g3" in d["kernel"]
+    executed = dc["flops"] * 6 // 8 if g3 else dc["flops"]
     if d["bound"] == "hbm":
         roof = {"bound": "hbm", "achieved": round(dc["bytes"] / dt / 1e9, 1), "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": round(dc["bytes"] / dt / HBM_PEAK, 4)}
     else:
         roof = {"bound": "mfma", "achieved": round(dc["flops"] / dt / 1e12, 2), "peak": FP64_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": round(dc["flops"] / dt / FP64_PEAK, 4)}
+                "unit": "TFLOP/s", "frac": round(dc["flops"] / dt / FP64_PEAK, 4),
+                "executed_flops": executed, "executed_TFLOPs": round(executed / dt / 1e12, 2),
+                "executed_frac": round(executed / dt / FP64_PEAK, 4),
+                "peak_measured_mfma_f64": peaks["mfma_f64"]["best_TFLOPs"],
+                "frac_of_measured_mfma_f64": round(executed / dt / 1e12 / peaks["mfma_f64"]["best_TFLOPs"], 4)}
     from paper_1905_03136_amd import codegen, profile_summary
     src_hash = profile_summary.source_hash()
     symbol = codegen.kernel_symbol(d["kernel"])
     roof.update({"kernel": d["kernel"], "kernel_symbol": symbol, "avg_us": d["us"], "bytes": dc["bytes"],
-                 "flops": dc["flops"], "traffic": None,
+                 "flops": dc["flops"], "traffic": None, "timing": "median over the timed steps (HIP events on "
+                 "the launch stream)",
                  "per_launch": "%s %s M=%d N=%d K=%d: %d algorithmic bytes, %d flops" % (
                      d["op"], d["dtype"], d["M"], d["N"], K, dc["bytes"], dc["flops"])})
     # HBM bytes per launch from the committed counter summary of this step alone
@@ -400,6 +682,11 @@ def main():
     if rec:
         roof["traffic"] = rec["traffic"]
         roof["traffic_source"] = "profiles/" + os.path.basename(f)
+        # the same fraction from the profiler's kernel trace of that run
+        tt = rec["avg_us"] * 1e-6
+        roof["trace_avg_us"] = rec["avg_us"]
+        roof["frac_trace"] = round((dc["bytes"] / tt / HBM_PEAK) if d["bound"] == "hbm" else
+                                   (dc["flops"] / tt / FP64_PEAK), 4)
 
     if not a.no_check:
         # spot check of the timed buffers: one TSMTTSM entry against a direct FP64 dot product
@@ -422,6 +709,8 @@ def main():
                 "note": "measured with the library's stream probes over 8 GiB; roof_frac_bs uses b_s "
                         "(read for TSMTTSM, copy for TSMM) instead of the 8 TB/s spec"},
         "widths": per,
+        "fp64_peaks_measured": peaks,
+        "gpu_state": {"before": gpu_before, "after": gpu_after},
     }
     if not a.no_forms:
         del bufs, calls
@@ -432,6 +721,11 @@ def main():
         print("[bench] batched form (64 orthogonalisation steps, one persistent launch)", file=sys.stderr,
               flush=True)
         out["batched_form"] = batched_form(torch, api, inputs, dev)
+        torch.cuda.empty_cache()
+        print("[bench] small-K leg (TSMTTSM D K=2^20 M=N=4) and autograd leg (K=2^22, 32x32)", file=sys.stderr,
+              flush=True)
+        out["small_k"] = small_k_leg(torch, api, inputs, dev)
+        out["autograd_form"] = autograd_leg(torch, inputs, dev)
     if a.cpu_sample > 0:
         print("[bench] timing the CPU oracle on a %d-row sample" % a.cpu_sample, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_sample)
