@@ -436,7 +436,8 @@ def fp64_peaks(torch, occs=(1, 2, 4, 8), iters=20000):
             def run():
                 st, fl[0] = _lib.tsg_peak_probe(kind, occ, iters, s)
                 _lib.check(st)
-            per[str(occ)] = round(fl[0] / time_call(torch, run, reps=3) / 1e12, 2)
+            t = time_call(torch, run, reps=3)   # runs the probe, which sets fl[0]
+            per[str(occ)] = round(fl[0] / t / 1e12, 2)
         out[name] = {"TFLOPs_by_blocks_per_cu": per, "best_TFLOPs": max(per.values())}
     return out
 

@@ -78,13 +78,21 @@ stream_mix(const d2* __restrict__ x, int64_t nch, d2* __restrict__ y, int64_t ch
 #pragma unroll
         for (int u = 0; u < ILP; ++u) t += v[u];
         s += t.x + t.y;
+        // element i of the chunk of y takes v[(i / kThreads) % ILP]; the
+        // register index is a compile-time constant (a run-time index would
+        // put v in scratch memory)
         d2* q = y + c * chy;
-        for (int64_t i = threadIdx.x; i < chy; i += kThreads) {
-            const d2 w = v[(i / kThreads) % ILP];
-            if constexpr (NT)
-                __builtin_nontemporal_store(w, q + i);
-            else
-                q[i] = w;
+        for (int64_t i0 = 0; i0 < chy; i0 += CH) {
+#pragma unroll
+            for (int u = 0; u < ILP; ++u) {
+                const int64_t i = i0 + (int64_t)u * kThreads + threadIdx.x;
+                if (i < chy) {
+                    if constexpr (NT)
+                        __builtin_nontemporal_store(v[u], q + i);
+                    else
+                        q[i] = v[u];
+                }
+            }
         }
     }
     if (s == 1.2345e-300) sink[blockIdx.x] = s;

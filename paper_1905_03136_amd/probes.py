@@ -75,7 +75,8 @@ def mixes(x, y, ratios=((1, 0), (1, 1), (4, 1), (1, 4), (2, 1), (1, 2)), occs=(2
                         st, moved[0] = _lib.tsg_stream_probe(x.data_ptr(), xb, y.data_ptr() if wr else None, yb,
                                                              occ, ilp, nt, s)
                         _lib.check(st)
-                    bw = moved[0] / _time(run) / 1e9
+                    t = _time(run)          # runs the probe, which sets moved[0]
+                    bw = moved[0] / t / 1e9
                     if bw > best[0]:
                         best = (bw, (occ, ilp))
             key = "%d:%d %s" % (rd, wr, "streaming" if nt else "cached")
@@ -101,7 +102,8 @@ def peaks(occs=(1, 2, 4, 8), iters=20000):
             def run():
                 st, fl[0] = _lib.tsg_peak_probe(kind, occ, iters, s)
                 _lib.check(st)
-            rate = fl[0] / _time(run, reps=3) / 1e12
+            t = _time(run, reps=3)      # runs the probe, which sets fl[0]
+            rate = fl[0] / t / 1e12
             out[name][str(occ)] = rate
             print("[probe] %-9s blocks/CU %d: %6.1f TF/s" % (name, occ, rate), flush=True)
     return out
