@@ -560,6 +560,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="rows of the oracle sample (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the post-run spot check")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched form measurements")
+    ap.add_argument("--no-smi", action="store_true", help="do not query rocm-smi for clocks and power")
     ap.add_argument("--all-widths", action="store_true",
                     help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
     ap.add_argument("--vendor", action="store_true",
@@ -626,7 +627,7 @@ def main():
           % (bs["read"] / 1e9, bs["copy"] / 1e9, a.steps), file=sys.stderr, flush=True)
     evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
            for _ in range(a.steps)]
-    gpu_before = gpu_state()
+    gpu_before = None if a.no_smi else gpu_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
@@ -634,7 +635,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
-    gpu_after = gpu_state()
+    gpu_after = None if a.no_smi else gpu_state()
     per = []
     for i, c in enumerate(calls):
         ts = sorted(evs[s][i][0].elapsed_time(evs[s][i][1]) * 1e-3 for s in range(a.steps))

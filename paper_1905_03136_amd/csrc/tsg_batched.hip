@@ -712,7 +712,7 @@ orth_persistent(const DevDesc* __restrict__ descs, const Item* __restrict__ item
 }
 
 // ------------------------------------------------------------ work queue
-// Slab height of an instance: rows_fixed if positive, else about kItemBytes
+// Slab height of an instance: rows_fixed if positive, else about item_bytes
 // of input per slab and at most kMaxSlabs slabs; never more rows than keep
 // the byte offsets inside a slab (plus one step past its end) below 2^31.
 // Returns 0 if no height fits (leading dimensions too large).  Shared by the
@@ -725,12 +725,13 @@ __host__ __device__ inline int64_t slab_limit(int64_t ldv, int64_t ldw)
     return ((((int64_t)1 << 31) / (8 * ld)) - 128) / 16 * 16;
 }
 
-__host__ __device__ inline int64_t slab_rows(int64_t K, int M, int N, int64_t ldv, int64_t ldw, int64_t rows_fixed)
+__host__ __device__ inline int64_t slab_rows(int64_t K, int M, int N, int64_t ldv, int64_t ldw, int64_t rows_fixed,
+                                             int64_t item_bytes)
 {
     const int64_t lim = slab_limit(ldv, ldw);
     int64_t R = rows_fixed;
     if (R <= 0) {
-        const int64_t want = round16(kItemBytes / (8 * (int64_t)(M + N)));
+        const int64_t want = round16(item_bytes / (8 * (int64_t)(M + N)));
         R = want > 16 ? want : 16;
         const int64_t few = round16((K + kMaxSlabs - 1) / kMaxSlabs);
         R = R > few ? R : few;
@@ -794,8 +795,8 @@ __host__ __device__ inline Layout make_layout(int count, int64_t max_items, int6
 // times that into half slabs), so the blocks still running after the queue
 // drains hold short items.
 __global__ void __launch_bounds__(kMaxCount)
-orth_setup(const tsg_orth_desc* __restrict__ in, int count, int64_t rows_fixed, int lag, int resident,
-           unsigned spin, Ctrl* __restrict__ ctrl, DevDesc* __restrict__ dd, unsigned* __restrict__ flags,
+orth_setup(const tsg_orth_desc* __restrict__ in, int count, int64_t rows_fixed, int64_t item_bytes, int lag,
+           int resident, unsigned spin, Ctrl* __restrict__ ctrl, DevDesc* __restrict__ dd, unsigned* __restrict__ flags,
            Item* __restrict__ items, int64_t max_items, int64_t max_parts)
 {
     // 56 KB: per instance its size key (then K), slab height, first partial
@@ -816,7 +817,7 @@ orth_setup(const tsg_orth_desc* __restrict__ in, int count, int64_t rows_fixed, 
                              reinterpret_cast<uintptr_t>(x.C);
         bool ok = x.K >= 0 && x.M >= 1 && x.N >= 1 && x.M <= kMaxM && x.N <= kMaxN && x.ldv >= x.M &&
                   x.ldw >= x.N && x.ldc >= x.N && x.C && (x.K == 0 || (x.V && x.W)) && al % sizeof(double) == 0;
-        const int64_t R = ok ? slab_rows(x.K, x.M, x.N, x.ldv, x.ldw, rows_fixed) : 0;
+        const int64_t R = ok ? slab_rows(x.K, x.M, x.N, x.ldv, x.ldw, rows_fixed, item_bytes) : 0;
         const int64_t nsl = x.K > 0 && R > 0 ? (x.K + R - 1) / R : 1;  // K = 0: one empty slab sets C = 0
         ok = ok && R > 0 && nsl <= ((int64_t)1 << 24);
         if (!ok) atomicOr(&s_err, kErrDesc);
@@ -986,11 +987,20 @@ int64_t resident_blocks(int* dev_out)
     return (int64_t)cus * std::max(occ, 1);
 }
 
+// Input bytes per slab under automatic sizing; TSG_ORTH_ITEM_BYTES overrides
+// it for tuning (values outside [64 KiB, 1 GiB] are ignored).
+int64_t item_bytes()
+{
+    const char* v = getenv("TSG_ORTH_ITEM_BYTES");
+    const long long b = v ? atoll(v) : 0;
+    return (b >= (64 << 10) && b <= (1 << 30)) ? (int64_t)b : kItemBytes;
+}
+
 hipError_t launch_setup(const tsg_orth_desc* d_in, int count, int64_t rows_fixed, int lag, int resident, void* ws,
                         const Layout& L, hipStream_t s)
 {
-    hipLaunchKernelGGL(orth_setup, dim3(1), dim3(kMaxCount), 0, s, d_in, count, rows_fixed, lag, resident,
-                       kDefaultSpin, at<Ctrl>(ws, L.ctrl), at<DevDesc>(ws, L.descs), at<unsigned>(ws, L.flags),
+    hipLaunchKernelGGL(orth_setup, dim3(1), dim3(kMaxCount), 0, s, d_in, count, rows_fixed, item_bytes(), lag,
+                       resident, kDefaultSpin, at<Ctrl>(ws, L.ctrl), at<DevDesc>(ws, L.descs), at<unsigned>(ws, L.flags),
                        at<Item>(ws, L.items), L.max_items, L.max_parts);
     return hipGetLastError();
 }
@@ -1060,7 +1070,7 @@ tsg_status tsg_orth_plan_create(tsg_orth_plan* plan, int32_t count, const tsg_or
         if ((reinterpret_cast<uintptr_t>(s.V) | reinterpret_cast<uintptr_t>(s.W) |
              reinterpret_cast<uintptr_t>(s.C)) % sizeof(double))
             return fail(TSG_E_ARG, "instance %lld: pointer not aligned to 8 bytes", i);
-        const int64_t R = slab_rows(s.K, s.M, s.N, s.ldv, s.ldw, rows_per_item);
+        const int64_t R = slab_rows(s.K, s.M, s.N, s.ldv, s.ldw, rows_per_item, item_bytes());
         if (R < 1)
             return fail(TSG_E_UNSUPPORTED, "instance %lld: slab height must be in [1, %lld] for its leading dimensions",
                         i, slab_limit(s.ldv, s.ldw));
@@ -1185,7 +1195,7 @@ namespace tsg {
 size_t orth_workspace_size(int64_t K, int32_t M, int32_t N, int32_t count)
 {
     if (K < 0 || M < 1 || N < 1 || M > kMaxM || N > kMaxN || count < 1 || count > kMaxCount) return 0;
-    const int64_t R = slab_rows(K, M, N, M, N, 0);
+    const int64_t R = slab_rows(K, M, N, M, N, 0, item_bytes());
     const int64_t nslab = K > 0 && R > 0 ? (K + R - 1) / R : 1;
     return make_layout(count, kItemsPerInstance * count, (int64_t)count * nslab * M * N).bytes;
 }

@@ -216,17 +216,9 @@ def write_table(db_path, out_path, merge=None):
     are kept."""
     from paper_1905_03136_amd.codegen import A32_TWIN, needs_layout
     best, plain = {}, {}
-    # binary32-arithmetic (op, dtype, M, N) that the database timed: only those
-    # get an entry (built from their own and their twin's records)
-    seen_a32 = set()
-    with open(db_path) as f:
-        for line in f:
-            try:
-                r = json.loads(line)
-            except ValueError:
-                continue
-            if r.get("dt") in A32_TWIN:
-                seen_a32.add((r["op"], r["dt"], r["M"], r["N"]))
+    # a binary32-arithmetic type takes the fastest of its own records and its
+    # binary64-arithmetic twin's (the twin is exact in its products and wins
+    # wherever it is as fast); tune both types in one run
     if merge and os.path.exists(merge):
         with open(merge) as f:
             for e in json.load(f).get("entries", []):
@@ -246,8 +238,6 @@ def write_table(db_path, out_path, merge=None):
             # a binary64-arithmetic kernel also serves its binary32-arithmetic twin type
             keys += [(r["op"], a, r["M"], r["N"]) for a, t in A32_TWIN.items() if t == r["dt"]]
             for key in keys:
-                if key[1] != r["dt"] and key not in seen_a32:
-                    continue
                 if key not in best or best[key].get("_kept") or r["us"] < best[key]["us"]:
                     best[key] = r
                 # fastest configuration without layout requirements on A
