@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kThreads) peak_mfma_f32(int64_t iters, double 
     if (t == 1.2345e-30f) sink[blockIdx.x] = t;
 }
 
-constexpr int kValuChains = 16;
+constexpr int kValuChains = 24;
 __global__ void __launch_bounds__(kThreads) peak_valu_f64(int64_t iters, double a, double* __restrict__ sink)
 {
     double acc[kValuChains];
