@@ -102,7 +102,7 @@ def generate(widths=None, variants=None, gen_dir=GEN):
     from paper_1905_03136_amd import codegen
     if variants is None:
         variants = codegen.all_variants(widths, os.path.join(HERE, "tuned.json"))
-    return codegen.emit(gen_dir, variants), variants
+    return codegen.emit(gen_dir, variants, batched=codegen.tuned_batched(os.path.join(HERE, "tuned.json"))), variants
 
 
 def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, lib_path=LIB, tag=""):
@@ -152,7 +152,8 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
         print("[build] %d variant(s) spill registers and are left out of the registry: %s"
               % (len(spilled), ", ".join(sorted(spilled))), flush=True)
         from paper_1905_03136_amd import codegen
-        codegen.emit(gen_dir, variants, exclude=spilled)
+        codegen.emit(gen_dir, variants, exclude=spilled,
+                     batched=codegen.tuned_batched(os.path.join(HERE, "tuned.json")))
     compile_all([table], "registry table")
     with open(stamp, "w") as f:
         f.write(flags)

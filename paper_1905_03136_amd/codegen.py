@@ -82,6 +82,57 @@ def candidates(op, dt, M, N):
     out = _candidates(op, dt, M, N)
     if is_f32(dt):
         out = [c for c in out if c["kind"] != "valu" and not c.get("VA")]
+    else:
+        out += _lds_candidates(op, dt, M, N)
+    return out
+
+
+LDS_BYTES = 160 * 1024  # LDS of one compute unit (gfx950)
+
+
+def _lds_candidates(op, dt, M, N):
+    """TSMTTSM with the rows staged in LDS by direct loads (tsmttsm_lds) for
+    widths above 16: WM x WN waves of MB x NB blocks of 16 x 16 cover C,
+    stages of RT rows, two stages in LDS.  Register model in doubles per
+    lane: accumulators plus the operands of one stage; two blocks per
+    compute unit (OCC = 2) where their LDS fits."""
+    out = []
+    if op != "tsmttsm" or (M <= 16 and N <= 16):
+        return out
+    cplx = DTYPES[dt][1]
+    cw = 2 if cplx else 1
+    if M * cw < 2 or N * cw < 2:
+        return out
+    mbt, nbt = _ceil(M, 16), _ceil(N, 16)
+    for wm in (1, 2, 4, 8):
+        for wn in (1, 2, 4, 8):
+            if wm * wn not in (2, 4, 8) or wm > mbt or wn > nbt:
+                continue
+            mb, nb = _ceil(mbt, wm), _ceil(nbt, wn)
+            if (wm - 1) * mb >= mbt or (wn - 1) * nb >= nbt:
+                continue  # a wave without a block of C
+            for g3 in ((0, 1) if cplx else (0,)):
+                acc = mb * nb * 4 * (3 if g3 else cw)
+                if acc > 64:
+                    continue
+                for rt in (16, 32, 64):
+                    ops = (rt // 4) * (mb + nb) * cw
+                    if acc + ops > 104:
+                        continue
+                    stage = 2 * (_ceil(rt * M * cw, 128) + _ceil(rt * N * cw, 128)) * 128 * 8
+                    lds = max(stage, M * N * cw * 8)
+                    if lds > LDS_BYTES:
+                        continue
+                    for occ in (1, 2, 4):
+                        # at most two waves per SIMD: the stage operands need the registers
+                        if occ > 1 and (occ * wm * wn > 8 or occ * lds > LDS_BYTES):
+                            continue
+                        c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wm * wn)
+                        if occ > 1:
+                            c["OCC"] = occ
+                        if g3:
+                            c["G3"] = 1
+                        out.append(c)
     return out
 
 
@@ -467,6 +518,8 @@ def variant_name(v):
         tag = "a32_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
     elif c["kind"] == "a32":
         tag = "a32_s%dn%d_u%d" % (c["MS"], c["NB"], c["U"])
+    elif c["kind"] == "lds":
+        tag = "lds_b%dx%dw%dx%d_k%d" % (c["MB"], c["NB"], c["WM"], c["WN"], c["RT"])
     elif v["op"] == "tsmttsm":
         tag = "mfma_b%dx%dw%d_u%d" % (c["MB"], c["NB"], c["MW"], c["U"])
     else:
@@ -504,6 +557,10 @@ def _template(v):
     if c["kind"] == "a32":
         return "tsg::tsmm_a32<%d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
             M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, c.get("FL", 0), "true" if c.get("RB") else "false")
+    if c["kind"] == "lds":
+        return "tsg::tsmttsm_lds<%d, %d, %d, %d, %d, %d, %d, %s, %s, %d>" % (
+            M, N, c["MB"], c["NB"], c["WM"], c["WN"], c["RT"], cplx, "true" if c.get("G3") else "false",
+            c.get("OCC", 1))
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
@@ -527,6 +584,8 @@ def rows_per_tile(v):
     c = v["cfg"]
     if c["kind"] == "packed":
         return (4 if v["op"] == "tsmttsm" else 16) * c["U"] * c["WPB"]
+    if c["kind"] == "lds":
+        return c["RT"]
     if v["op"] == "tsmttsm":
         return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])  # mfma, a32
     return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 16 * c["U"] * c["WPB"]
@@ -555,19 +614,38 @@ def _record(v, fn):
     pair_x = int((c["kind"] == "valu" and bool(c.get("VB"))) or (v["op"] == "tsmttsm" and slab_pairs))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)
-    flat_a = int(bool(c.get("FL")))
+    flat_a = int(bool(c.get("FL")) or c["kind"] == "lds")
     read_b = int(bool(c.get("RB")))
-    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
+    align16 = int(c["kind"] == "lds")
+    return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
             % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
-               64 * c["WPB"], rows_per_tile(v), pack, flat_a, read_b, variant_name(v),
+               64 * c["WPB"], rows_per_tile(v), pack, flat_a, read_b, align16, variant_name(v),
                fn.replace("launch_", "kernel_"), fn))
 
 
-def emit(outdir, variants, per_file=6, exclude=()):
+# batched orthogonalisation: input bytes per slab and queue interleave (0: every
+# slab item before any update item), used until the autotuner has chosen
+ORTH_DEFAULTS = {"item_bytes": 4 << 20, "lag": 0}
+
+
+def tuned_batched(path):
+    """The batched form's parameters chosen by the autotuner (tuned.json key
+    "batched"), else ORTH_DEFAULTS."""
+    out = dict(ORTH_DEFAULTS)
+    if path and os.path.exists(path):
+        with open(path) as f:
+            b = json.load(f).get("batched") or {}
+        out.update({k: int(b[k]) for k in ORTH_DEFAULTS if k in b})
+    return out
+
+
+def emit(outdir, variants, per_file=6, exclude=(), batched=None):
     """Write gen/tsg_gen_XX.hip (instantiations + launchers) and gen/tsg_table.hip.
     Returns the list of written source files.  Files are only rewritten when
     their text changes, so unchanged units need no recompilation.  Variants
-    named in ``exclude`` are compiled but left out of the registry table."""
+    named in ``exclude`` are compiled but left out of the registry table;
+    ``batched`` holds the batched form's tuned parameters."""
+    batched = dict(ORTH_DEFAULTS, **(batched or {}))
     os.makedirs(outdir, exist_ok=True)
     files = []
     recs = []
@@ -595,7 +673,10 @@ def emit(outdir, variants, per_file=6, exclude=()):
                  "const Variant kVariants[] = {\n")
     for v, fn in recs:
         table.append(_record(v, fn))
-    table.append("};\nconst int kNumVariants = %d;\n}  // namespace tsg\n#endif\n" % len(recs))
+    table.append("};\nconst int kNumVariants = %d;\n"
+                 "// batched orthogonalisation (autotuned): input bytes per slab, queue interleave\n"
+                 "const int64_t kOrthItemBytes = %d;\nconst int kOrthLag = %d;\n"
+                 "}  // namespace tsg\n#endif\n" % (len(recs), batched["item_bytes"], batched["lag"]))
     path = os.path.join(outdir, "tsg_table.hip")
     _write_if_changed(path, "".join(table))
     files.append(path)

@@ -29,6 +29,7 @@
 
 #include "../../include/tsgemm.h"
 #include "tsg_device.hpp"
+#include "tsg_registry.hpp"
 
 namespace tsg {
 tsg_status report(tsg_status s, const char* msg);  // sets the detail of tsg_last_error()
@@ -46,7 +47,6 @@ constexpr unsigned kDefaultSpin = 1u << 23;   // sleeps of ~0.2 us: about 2 s
 constexpr int64_t kItemBytes = 4 << 20;       // input bytes of one slab (automatic sizing; 4 MB measured
                                               // 3% faster than 2 MB and 8 MB on the 64-instance workload)
 constexpr int64_t kMaxSlabs = 256;            // slabs per instance (bounds the fold)
-constexpr int kDefaultLag = 0;                // instances between an instance's slab items and its updates (0: all)
 
 struct Item {
     int64_t row0;      // first row of the slab
@@ -987,13 +987,15 @@ int64_t resident_blocks(int* dev_out)
     return (int64_t)cus * std::max(occ, 1);
 }
 
-// Input bytes per slab under automatic sizing; TSG_ORTH_ITEM_BYTES overrides
-// it for tuning (values outside [64 KiB, 1 GiB] are ignored).
+// Input bytes per slab under automatic sizing: the autotuner's choice
+// (generated table), which TSG_ORTH_ITEM_BYTES overrides while tuning (values
+// outside [64 KiB, 1 GiB] are ignored).
 int64_t item_bytes()
 {
     const char* v = getenv("TSG_ORTH_ITEM_BYTES");
     const long long b = v ? atoll(v) : 0;
-    return (b >= (64 << 10) && b <= (1 << 30)) ? (int64_t)b : kItemBytes;
+    if (b >= (64 << 10) && b <= (1 << 30)) return (int64_t)b;
+    return (tsg::kOrthItemBytes >= (64 << 10) && tsg::kOrthItemBytes <= (1 << 30)) ? tsg::kOrthItemBytes : kItemBytes;
 }
 
 hipError_t launch_setup(const tsg_orth_desc* d_in, int count, int64_t rows_fixed, int lag, int resident, void* ws,
@@ -1019,7 +1021,7 @@ hipError_t launch_persistent(void* ws, const Layout& L, int count, int grid, hip
 int queue_lag(int count)
 {
     const char* v = getenv("TSG_ORTH_LAG");
-    const int lag = v ? atoi(v) : kDefaultLag;
+    const int lag = v ? atoi(v) : tsg::kOrthLag;
     return lag < 1 ? count : std::min(lag, count);
 }
 

@@ -511,6 +511,211 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 }
 
 // ============================================================================
+// TSMTTSM on the matrix cores with the rows staged in LDS by direct loads.
+//
+// The register-ring kernels above hold the next tile's operands in VGPRs
+// while the current tile is multiplied, so how far ahead they can load is
+// set by the register file, and at the wide widths (complex 33..64, real
+// 49..64) the rings that would hide the memory latency spill.  Here the rows
+// travel from HBM straight into LDS (global_load_lds_dwordx4: each lane
+// brings 16 bytes, a wave 1 KB of consecutive bytes, with no VGPR holding
+// the data) in stages of RT rows shared by the whole block, two stages in
+// turn: while the matrix cores work on stage t, stage t + 1 is in flight.
+// Each wave reads the operands of its own blocks of C for the whole stage
+// into registers (the matrix-core operand layout of tsmttsm_mfma) right after
+// the barrier that publishes the stage, then issues the loads of the next
+// stage into the other buffer and multiplies.  A block of WM x WN waves
+// covers C with MB x NB blocks of 16 x 16 per wave; every wave reads every
+// row of the stage, each element of A and B crosses HBM once.
+//
+// Needs lda = M and ldb = N (a stage is one contiguous run of A and one of
+// B) and 16-byte aligned A and B.  Lane addresses past the end of a matrix
+// are clamped to its last 16 bytes; the rows they fill (past K) are zeroed
+// when read from LDS.
+// ============================================================================
+
+// One wave-wide direct load: 64 lanes x 16 bytes from src + 2 lane (doubles)
+// into 1 KB of LDS at dst (the hardware places lane l at dst + 16 l).
+__device__ __forceinline__ void dma16(const double* src, double* dst)
+{
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+
+template <int MC, int NC, int MB, int NB, int WM, int WN, int RT, bool CPLX, bool G3 = false, int OCC = 1>
+__global__ void __launch_bounds__(WM * WN * kWave, OCC)
+tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+            const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
+            double* __restrict__ ws, int conj)
+{
+    using T = elem_t<CPLX>;
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int WPB = WM * WN;
+    constexpr int KS = RT / 4;                                   // 4-row steps of a stage
+    static_assert(MC > 0 && NC > 0 && RT % 4 == 0 && RT % 2 == 0, "compile-time widths, stages of 4-row steps");
+    static_assert(WM * MB * 16 >= MC && WN * NB * 16 >= NC, "the waves' blocks cover C");
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
+    constexpr int SA = ((RT * MC * CW + 127) / 128) * 128;       // doubles of A per stage (whole 1 KB loads)
+    constexpr int SB = ((RT * NC * CW + 127) / 128) * 128;
+    constexpr int SS = SA + SB;                                   // one stage
+    constexpr int E = MC * NC * CW;
+    constexpr int LDSN = 2 * SS > E ? 2 * SS : E;                 // two stages; the partial reuses them
+    constexpr int NLA = SA / 128, NLB = SB / 128;                 // wave loads per stage
+    __shared__ __attribute__((aligned(16))) double lds[LDSN];
+
+    const double* __restrict__ A = static_cast<const double*>(Av);
+    const double* __restrict__ B = static_cast<const double*>(Bv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wm = wave % WM, wn = wave / WM;
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+    const int64_t totA = K * (int64_t)(MC * CW), totB = K * (int64_t)(NC * CW);   // doubles
+    const int64_t lastA = (totA - 2) & ~(int64_t)1, lastB = (totB - 2) & ~(int64_t)1;
+
+    // the stage of tile t into buffer b: wave w issues loads w, w + WPB, ...
+    auto stage = [&](int64_t t, int b) {
+        double* dst = lds + b * SS;
+        const int64_t ea = t * (int64_t)(RT * MC * CW), eb = t * (int64_t)(RT * NC * CW);
+#pragma unroll
+        for (int i = wave; i < NLA + NLB; i += WPB) {
+            if (i < NLA) {
+                const int64_t e = ea + (int64_t)i * 128 + 2 * lane;
+                dma16(A + (e <= lastA ? e : lastA), dst + i * 128);
+            } else {
+                const int64_t e = eb + (int64_t)(i - NLA) * 128 + 2 * lane;
+                dma16(B + (e <= lastB ? e : lastB), dst + SA + (i - NLA) * 128);
+            }
+        }
+    };
+
+    // columns of the wave's blocks; lanes past a width read column 0 of the
+    // same row (those products reach only entries of C that are not stored)
+    int moff[MB], noff[NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int m = (wm * MB + i) * 16 + lc;
+        moff[i] = m < MC ? m : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int n = (wn * NB + j) * 16 + lc;
+        noff[j] = n < NC ? n : 0;
+    }
+
+    dbl4 acc[MB][NB];
+    dbl4 acci[CPLX ? MB : 1][CPLX ? NB : 1];
+    dbl4 accs[G3 ? MB : 1][G3 ? NB : 1];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (CPLX) acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (G3) accs[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+
+    const int64_t ntiles = (K + RT - 1) / RT;
+    const int64_t G = gridDim.x;
+    int64_t t = blockIdx.x;
+    if (t < ntiles) stage(t, 0);
+    for (int b = 0; t < ntiles; t += G, b ^= 1) {
+        // every wave's loads of stage t have landed; every wave is done with
+        // the other buffer (its reads completed before it reached here)
+        __syncthreads();
+        const double* sa = lds + b * SS;
+        const double* sb = sa + SA;
+        T av[KS][MB], bv[KS][NB];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bool ok = t * RT + 4 * s + lr < K;
+            const int r = 4 * s + lr;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) av[s][i] = keep(ok, lds_elem(sa, r * MC + moff[i], T{}));
+#pragma unroll
+            for (int j = 0; j < NB; ++j) bv[s][j] = keep(ok, lds_elem(sb, r * NC + noff[j], T{}));
+        }
+        if (t + G < ntiles) stage(t + G, b ^ 1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if constexpr (!CPLX) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(av[s][i], bv[s][j], acc[i][j]);
+            } else if constexpr (G3) {
+                double ai[MB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) ai[i] = conj ? -av[s][i].im : av[s][i].im;
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acc[i][j] = mfma16(av[s][i].re, bv[s][j].re, acc[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) acci[i][j] = mfma16(ai[i], bv[s][j].im, acci[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i) ai[i] += av[s][i].re;  // Ar + Ai
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const double sbj = bv[s][j].re + bv[s][j].im;
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) accs[i][j] = mfma16(ai[i], sbj, accs[i][j]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        acc[i][j] = mfma16(av[s][i].re, bv[s][j].re, acc[i][j]);
+                        acci[i][j] = mfma16(av[s][i].re, bv[s][j].im, acci[i][j]);
+                    }
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    const double ai = conj ? -av[s][i].im : av[s][i].im;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        acc[i][j] = mfma16(ai, -bv[s][j].im, acc[i][j]);
+                        acci[i][j] = mfma16(ai, bv[s][j].re, acci[i][j]);
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (G3) {
+        // Cr = P1 - P2, Ci = P3 - P1 - P2
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const dbl4 p1 = acc[i][j], p2 = acci[i][j];
+                acc[i][j] = p1 - p2;
+                acci[i][j] = accs[i][j] - p1 - p2;
+            }
+    }
+    // the waves own disjoint blocks of C: the block partial is written
+    // directly (into the stage buffers, free once every wave is here)
+    __syncthreads();
+    double* part = lds;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = (wm * MB + i) * 16 + lr + 4 * r;
+                const int n = (wn * NB + j) * 16 + lc;
+                if (m < MC && n < NC) {
+                    const int e = (m * NC + n) * CW;
+                    part[e] = acc[i][j][r];
+                    if constexpr (CPLX) part[e + 1] = acci[i][j][r];
+                }
+            }
+    __syncthreads();
+    block_out<CW>(part, E, NC, ws, C, ldc);
+}
+
+// ============================================================================
 // TSMTTSM on the matrix cores for narrow widths (M, N <= 16): row packing.
 //
 // With M, N < 16 a plain 16 x 16 fragment would leave most lanes idle and

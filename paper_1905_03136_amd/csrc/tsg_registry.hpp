@@ -41,6 +41,7 @@ struct Variant {
     int pack;           // row packing: 0 none, 1 P = 16 / max(M, N) (TSMTTSM), 2 P = 16 / N (TSMM)
     int flatA;          // reads the tall operands as runs of rows: needs lda == M (TSMTTSM: and ldb == N)
     int readB;          // TSMM reading the old B with A (serves only calls with beta != 0)
+    int align16;        // needs A and X 16-byte aligned (direct 16-byte loads into LDS)
     const char* name;
     const void* (*kernel)(); // device function, for occupancy queries
     void (*launch)(const Launch&);
@@ -48,5 +49,12 @@ struct Variant {
 
 extern const Variant kVariants[];
 extern const int kNumVariants;
+
+// Batched orthogonalisation parameters chosen by the autotuner (generated):
+// input bytes per slab under automatic sizing, and the queue interleave
+// (instances between an instance's slab items and its update items; 0: every
+// slab item before any update item).
+extern const int64_t kOrthItemBytes;
+extern const int kOrthLag;
 
 }  // namespace tsg

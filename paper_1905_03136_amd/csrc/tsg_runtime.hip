@@ -226,6 +226,7 @@ const tsg::Variant* pick_for(int op, int dt, int M, int N, const void* A, int64_
     const bool x_pairs = (ldx % 2 == 0) && aligned(X, 16);
     // slab reads: the rows of A (TSMTTSM: and of B) are one contiguous run
     const bool rows_contiguous = lda == M && (op != tsg::OP_TSMTTSM || ldx == N);
+    const bool ax16 = aligned(A, 16) && aligned(X, 16);
     const tsg::Variant* best = nullptr;
     if (!g_force.empty()) {
         for (int i = 0; i < tsg::kNumVariants; ++i) {
@@ -233,7 +234,7 @@ const tsg::Variant* pick_for(int op, int dt, int M, int N, const void* A, int64_
             if (g_force != v.name) continue;
             const bool serves = (v.M == M && v.N == N) || (v.M == 0 && M <= v.maxM && N <= v.maxN);
             if (v.op == op && v.dt == dt && serves && (!v.pairA || a_pairs) && (!v.pairX || x_pairs) &&
-                (!v.flatA || rows_contiguous) && (!v.readB || beta_nz))
+                (!v.flatA || rows_contiguous) && (!v.readB || beta_nz) && (!v.align16 || ax16))
                 return &v;
         }
         return nullptr;
@@ -245,6 +246,7 @@ const tsg::Variant* pick_for(int op, int dt, int M, int N, const void* A, int64_
         if (v.pairX && !x_pairs) continue;
         if (v.flatA && !rows_contiguous) continue;
         if (v.readB && !beta_nz) continue;
+        if (v.align16 && !ax16) continue;
         if (v.M == M && v.N == N) return &v;
         if (v.M == 0 && !best && M <= v.maxM && N <= v.maxN && (!v.evenW || (M % 2 == 0 && N % 2 == 0)))
             best = &v;

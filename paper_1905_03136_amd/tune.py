@@ -210,6 +210,74 @@ def cmd_run(args):
     write_table(args.db, args.out, args.merge)
 
 
+def cmd_batched(args):
+    """Autotune the batched form on its workload: every (input bytes per
+    slab, queue interleave) pair of the grid is timed on one persistent
+    launch of the batched orthogonalisation (``inputs.batched_instances``:
+    `count` instances, K_i log-uniform in [2^16, 2^22]); the fastest pair is
+    written to the table's "batched" key, from which the generator compiles
+    the library's defaults."""
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_1905_03136_amd import api, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shapes = inputs.batched_instances(args.count, seed=0)
+    pairs = []
+    for i, (K, M, N) in enumerate(shapes):
+        V = inputs.device_uniform(K, M, 100 + i, inputs.STREAM_V0, False, dev)
+        V.mul_((3.0 / K) ** 0.5)
+        W = inputs.device_uniform(K, N, 100 + i, inputs.STREAM_W0, False, dev)
+        pairs.append((V, W))
+    byts = sum(8 * K * (2 * M + 3 * N) for K, M, N in shapes)
+    db = open(args.db, "a")
+    recs = []
+    for ib in [int(x) for x in args.item_bytes.split(",")]:
+        for lag in [int(x) for x in args.lags.split(",")]:
+            os.environ["TSG_ORTH_ITEM_BYTES"] = str(ib)
+            os.environ["TSG_ORTH_LAG"] = str(lag)
+            plan = api.OrthPlan(pairs)
+            try:
+                for _ in range(args.warmup):
+                    plan.launch()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(args.reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    plan.launch()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                plan.check()
+            finally:
+                plan.close()
+            ts.sort()
+            rec = dict(form="batched", count=args.count, item_bytes=ib, lag=lag, us=round(ts[len(ts) // 2] * 1e6, 1),
+                       us_min=round(ts[0] * 1e6, 1), GBps=round(byts / ts[len(ts) // 2] / 1e9, 1))
+            recs.append(rec)
+            db.write(json.dumps(rec) + "\n")
+            db.flush()
+            print("[tune] batched item bytes %9d lag %3d: %8.1f us %7.1f GB/s" % (ib, lag, rec["us"], rec["GBps"]),
+                  flush=True)
+    db.close()
+    for k in ("TSG_ORTH_ITEM_BYTES", "TSG_ORTH_LAG"):
+        os.environ.pop(k, None)
+    best = min(recs, key=lambda r: r["us"])
+    tab = {"entries": []}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            tab = json.load(f)
+    tab["batched"] = dict(item_bytes=best["item_bytes"], lag=best["lag"], us=best["us"], GBps=best["GBps"],
+                          count=args.count, grid=[[r["item_bytes"], r["lag"], r["us"]] for r in recs])
+    with open(args.out, "w") as f:
+        json.dump(tab, f, indent=1)
+        f.write("\n")
+    print("[tune] batched: item bytes %d, lag %d (%.1f us); wrote %s" % (best["item_bytes"], best["lag"], best["us"],
+                                                                         args.out), flush=True)
+
+
 def write_table(db_path, out_path, merge=None):
     """Fastest correct configuration per (op, dtype, M, N) from the database;
     entries of an existing table ``merge`` that the database does not cover
@@ -251,8 +319,17 @@ def write_table(db_path, out_path, merge=None):
         if needs_layout(r["cfg"]) and k in plain:
             e.update(plain_cfg=plain[k]["cfg"], plain_name=plain[k]["name"], plain_us=plain[k]["us"])
         entries.append(e)
+    tab = {"entries": entries}
+    # the batched form's tuned parameters are kept from the merged table
+    for src in (merge, out_path):
+        if src and os.path.exists(src):
+            with open(src) as f:
+                b = json.load(f).get("batched")
+            if b:
+                tab["batched"] = b
+                break
     with open(out_path, "w") as f:
-        json.dump({"entries": entries}, f, indent=1)
+        json.dump(tab, f, indent=1)
         f.write("\n")
     print("[tune] wrote %s (%d entries)" % (out_path, len(entries)), flush=True)
 
@@ -336,6 +413,14 @@ def main(argv=None):
     ab = sub.add_parser("ablate", help="cost of fixing each design dimension, from tuning databases")
     ab.add_argument("--db", action="append", required=True, help="a tuning database (repeatable; later ones win)")
     ab.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
+    bt = sub.add_parser("batched", help="GPU: input bytes per slab and queue interleave of the batched form")
+    bt.add_argument("--count", type=int, default=64)
+    bt.add_argument("--item-bytes", default="1048576,2097152,4194304,8388608,16777216")
+    bt.add_argument("--lags", default="0,4,16,32")
+    bt.add_argument("--reps", type=int, default=5)
+    bt.add_argument("--warmup", type=int, default=2)
+    bt.add_argument("--db", default="gpurun_out/tune_batched.jsonl")
+    bt.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
     t = sub.add_parser("table")
     t.add_argument("--db", default="gpurun_out/tune_db.jsonl")
     t.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
@@ -347,6 +432,8 @@ def main(argv=None):
         cmd_run(a)
     elif a.cmd == "ablate":
         cmd_ablate(a)
+    elif a.cmd == "batched":
+        cmd_batched(a)
     else:
         write_table(a.db, a.out, a.merge)
 

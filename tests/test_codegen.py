@@ -72,3 +72,17 @@ def test_binary32_arithmetic_candidates_and_defaults():
     assert all(x["cfg"]["kind"] == "a32" for x in tv if x["M"] and codegen.is_a32(x["dt"]))
     names = {codegen.variant_name(x) for x in tv}
     assert "tsmttsm_r32a_32x32_a32_b2x2w1_u2" in names
+
+
+def test_batched_parameters_reach_the_generated_table(tmp_path):
+    """The autotuner's batched-form choice (tuned.json key "batched") is
+    compiled into the generated registry table; without it the defaults are."""
+    import json
+    tab = tmp_path / "tuned.json"
+    tab.write_text(json.dumps({"entries": [], "batched": {"item_bytes": 8388608, "lag": 16, "us": 1.0}}))
+    b = codegen.tuned_batched(str(tab))
+    assert b == {"item_bytes": 8388608, "lag": 16}
+    assert codegen.tuned_batched(str(tmp_path / "missing.json")) == codegen.ORTH_DEFAULTS
+    files = codegen.emit(str(tmp_path / "gen"), [], batched=b)
+    text = open([f for f in files if f.endswith("tsg_table.hip")][0]).read()
+    assert "const int64_t kOrthItemBytes = 8388608;" in text and "const int kOrthLag = 16;" in text

@@ -107,6 +107,34 @@ def test_orth_batched_strided():
     assert np.all(Cb[:, :5] == 7.0) and np.all(Cb[:, 16:] == 7.0)
 
 
+# strided instances (leading dimensions above the widths) of every width class
+# of the strided paths: updates in 1..16 four-column slices, partial sums in
+# 1..4 sixteen-column blocks
+STRIDED_M = [3, 4, 6, 11, 16, 19, 24, 27, 30, 36, 40, 44, 48, 52, 56, 60, 64]
+
+
+@pytest.mark.parametrize("rows_per_item", [0, 1200])
+def test_orth_batched_strided_every_width_class(rows_per_item):
+    print("orth strided width classes rows_per_item=%d" % rows_per_item, flush=True)
+    pairs, ref = [], []
+    for i, M in enumerate(STRIDED_M):
+        K, N = 3001 + 977 * i, 1 + (5 * i) % 16
+        V = inputs.host_integers(K, M + 3, 40, inputs.STREAM_A + 2 * i, False, -7, 8)
+        W = inputs.host_integers(K, N + 2, 40, inputs.STREAM_B + 2 * i, False, -7, 8)
+        dV, dW = dev(V), dev(W)
+        pairs.append((dV[:, 1:1 + M], dW[:, 2:2 + N]))
+        ref.append((np.ascontiguousarray(V[:, 1:1 + M]), np.ascontiguousarray(W[:, 2:2 + N]), dW, W))
+    C = api.orth_batched(pairs, rows_per_item=rows_per_item)
+    for i, ((V, W0, dW, Wfull), dC) in enumerate(zip(ref, C)):
+        C_ref, W_ref = oracle.orth_step(V, W0)
+        assert np.array_equal(host(dC), C_ref), "instance %d M=%d C" % (i, STRIDED_M[i])
+        Wn = host(dW)
+        N = W0.shape[1]
+        assert np.array_equal(Wn[:, 2:2 + N], W_ref), "instance %d M=%d W" % (i, STRIDED_M[i])
+        # the columns around the instance's W are untouched
+        assert np.array_equal(Wn[:, :2], Wfull[:, :2]) and np.array_equal(Wn[:, 2 + N:], Wfull[:, 2 + N:])
+
+
 def test_orth_batched_orthogonality():
     print("orth orthogonality", flush=True)
     shapes = [(131072, 64, 16), (100000, 32, 8), (65536, 16, 4), (80000, 8, 1), (70000, 4, 16)]
