@@ -19,6 +19,7 @@ autograd form (K = 2^22, M = N = 32).
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --all-widths      # every square width 1..64 instead (one JSON line each)
     python bench.py --all-widths --vendor   # ... with torch.matmul (rocBLAS / hipBLASLt) beside each
+    python bench.py --reduction-sweep       # TSMTTSM reduction variants against K (ablation)
 """
 import argparse
 import json
@@ -549,6 +550,54 @@ def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False):
     print(json.dumps({"all_widths_summary": summary}), flush=True)
 
 
+def reduction_sweep(torch, api, inputs, dev, widths=(4, 32), Ks=(10**3, 10**4, 10**5, 10**6, 10**7, 10**8),
+                    reps=20):
+    """Ablation of TSMTTSM's cross-block reduction against K (the paper's
+    Sections 3.2 and 5.5): the fixed-order two-kernel fold (the library's
+    default), global FP64 atomics of every block's partial into C, and no
+    reduction at all (the kernel alone: a lower bound), real data, M = N in
+    `widths`.  Per K up to 64 operand sets of at least 1 GiB together are used
+    in turn where they fit (small K stays cache resident, as in the paper's
+    sweep); median of `reps` event-timed calls.  One JSON line per (width, K)."""
+    from paper_1905_03136_amd import _lib
+    modes = (("fold", _lib.TSG_REDUCE_FOLD), ("atomic", _lib.TSG_REDUCE_ATOMIC), ("none", _lib.TSG_REDUCE_NONE))
+    for w in widths:
+        for K in Ks:
+            per = 8 * K * 2 * w
+            sets = max(1, min(64, -(-(1 << 30) // per)))
+            pairs = [(inputs.device_uniform(K, w, 60 + i, inputs.STREAM_A, False, dev),
+                      inputs.device_uniform(K, w, 60 + i, inputs.STREAM_B, False, dev)) for i in range(sets)]
+            C = torch.empty((w, w), dtype=torch.float64, device=dev)
+            byts, flops = algorithmic("tsmttsm", False, K, w, w)
+            rec = {"M": w, "N": w, "K": K, "sets": sets, "kernel": api.kernel_name("tsmttsm", torch.float64, w, w)}
+            try:
+                for name, mode in modes:
+                    _lib.check(_lib.tsg_set_reduction(mode))
+                    for a, b in pairs[:2]:
+                        api.tsmttsm(a, b, out=C)
+                    torch.cuda.synchronize()
+                    ts = []
+                    for r in range(reps):
+                        a, b = pairs[r % sets]
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        api.tsmttsm(a, b, out=C)
+                        e1.record()
+                        e1.synchronize()
+                        ts.append(e0.elapsed_time(e1) * 1e-3)
+                    ts.sort()
+                    t = ts[len(ts) // 2]
+                    rec[name] = {"us": round(t * 1e6, 2), "GBps": round(byts / t / 1e9, 1),
+                                 "roof_frac": round(roofline_time(byts, flops) / t, 4)}
+            finally:
+                _lib.tsg_set_reduction(_lib.TSG_REDUCE_FOLD)
+            for name in ("fold", "atomic"):
+                rec[name]["overhead_vs_none"] = round(rec[name]["us"] / rec["none"]["us"] - 1.0, 4)
+            print(json.dumps(rec), flush=True)
+            del pairs
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -563,6 +612,8 @@ def main():
     ap.add_argument("--no-smi", action="store_true", help="do not query rocm-smi for clocks and power")
     ap.add_argument("--all-widths", action="store_true",
                     help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
+    ap.add_argument("--reduction-sweep", action="store_true",
+                    help="instead of the bench step: TSMTTSM reduction variants (fold / atomic / none) against K")
     ap.add_argument("--vendor", action="store_true",
                     help="with --all-widths: also time torch.matmul (rocBLAS / hipBLASLt) on the same operands")
     a = ap.parse_args()
@@ -578,6 +629,9 @@ def main():
     torch.cuda.set_device(dev)
     if a.all_widths:
         all_widths(torch, api, inputs, dev, vendor=a.vendor)
+        return
+    if a.reduction_sweep:
+        reduction_sweep(torch, api, inputs, dev)
         return
     print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
     K = K_SWEEP

@@ -396,6 +396,20 @@ const char *tsg_variant_name(int32_t i);
  * different grouping, so floating-point results may differ in rounding). */
 tsg_status tsg_set_grid_limit(int32_t blocks);
 
+/* Ablation of the cross-block reduction of TSMTTSM (the paper's Section 3.2
+ * and 5.5 compare reduction variants against K).  Affects the calling
+ * thread's following TSMTTSM calls whose grid has more than one block:
+ *   TSG_REDUCE_FOLD    the default: per-block partials summed by a second
+ *                      kernel in a fixed order (bitwise reproducible);
+ *   TSG_REDUCE_ATOMIC  every block's partial added into C with global FP64
+ *                      atomics (C cleared first); the order of the additions
+ *                      and so the rounding varies from run to run;
+ *   TSG_REDUCE_NONE    no reduction: the partials stay in the workspace and C
+ *                      is NOT written (a timing lower bound only).
+ * Any other value returns TSG_E_ARG. */
+enum { TSG_REDUCE_FOLD = 0, TSG_REDUCE_ATOMIC = 1, TSG_REDUCE_NONE = 2 };
+tsg_status tsg_set_reduction(int32_t mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,7 @@ PROTOTYPES = {
     "tsg_latency_probe": (_i32, [_vp, _i64, _vp, _vp]),
     "tsg_force_variant": (_i32, [ctypes.c_char_p]),
     "tsg_set_grid_limit": (_i32, [_i32]),
+    "tsg_set_reduction": (_i32, [_i32]),
     "tsg_variant_count": (_i32, []),
     "tsg_variant_name": (ctypes.c_char_p, [_i32]),
 }
@@ -142,6 +143,13 @@ def tsg_force_variant(name):
 
 def tsg_set_grid_limit(blocks):
     return lib().tsg_set_grid_limit(blocks)
+
+
+TSG_REDUCE_FOLD, TSG_REDUCE_ATOMIC, TSG_REDUCE_NONE = 0, 1, 2
+
+
+def tsg_set_reduction(mode):
+    return lib().tsg_set_reduction(mode)
 
 
 def tsg_variant_count():

@@ -62,6 +62,28 @@ def _spilled(remarks):
     return out
 
 
+RESOURCES = ".res"  # per generated unit: register use of its kernels (JSON)
+
+
+def _resources(remarks):
+    """{mangled kernel name: {"vgpr", "agpr", "scratch", "occupancy"}} from
+    hipcc's resource-usage remarks."""
+    out, cur = {}, None
+    keys = {"VGPRs": "vgpr", "AGPRs": "agpr", "ScratchSize [bytes/lane]": "scratch",
+            "Occupancy [waves/SIMD]": "occupancy"}
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = m.group(1)
+            out[cur] = {}
+            continue
+        for k, name in keys.items():
+            m = re.search(re.escape(k) + r": (\d+)", line)
+            if m and cur:
+                out[cur][name] = int(m.group(1))
+    return out
+
+
 def _compile(src, obj, extra, resource=False):
     flags = ["-Rpass-analysis=kernel-resource-usage"] if resource else []
     cmd = [HIPCC, *CFLAGS, *extra, *flags, "-c", src, "-o", obj + ".tmp"]
@@ -72,8 +94,36 @@ def _compile(src, obj, extra, resource=False):
         with open(obj + SPILLS + ".tmp", "w") as f:
             f.write("".join(k + "\n" for k in _spilled(r.stdout)))
         os.replace(obj + SPILLS + ".tmp", obj + SPILLS)
+        import json
+        with open(obj + RESOURCES + ".tmp", "w") as f:
+            json.dump(_resources(r.stdout), f)
+        os.replace(obj + RESOURCES + ".tmp", obj + RESOURCES)
     os.replace(obj + ".tmp", obj)
     return src
+
+
+def variant_resources(variants, tag="_tune"):
+    """{variant name: register use} of the compiled units of a build (the
+    tuning library by default), from the per-unit resource records."""
+    import json
+    from paper_1905_03136_amd import codegen
+    mangled = {}
+    for f in glob.glob(os.path.join(OBJ + tag, "*" + RESOURCES)):
+        with open(f) as fh:
+            mangled.update(json.load(fh))
+    if not mangled:
+        return {}
+    keys = list(mangled)
+    r = subprocess.run(["c++filt"], input="\n".join(keys), stdout=subprocess.PIPE, text=True, check=True)
+    by_sym = {}
+    for k, d in zip(keys, r.stdout.splitlines()):
+        by_sym[d.split("(")[0]] = mangled[k]
+    out = {}
+    for v in variants:
+        sym = "void " + codegen.template_of(v)
+        if sym in by_sym:
+            out[codegen.variant_name(v)] = by_sym[sym]
+    return out
 
 
 def _spilled_variants(objs, variants):
@@ -132,7 +182,8 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
     def compile_all(sources, what):
         todo = [(s, obj_of[s]) for s in sources
                 if not same_flags or _stale(obj_of[s], [s] + HEADERS + ([] if s in units else [ABI_HEADER]))
-                or (s in units and not os.path.exists(obj_of[s] + SPILLS))]
+                or (s in units and not (os.path.exists(obj_of[s] + SPILLS) and
+                                        os.path.exists(obj_of[s] + RESOURCES)))]
         if not todo:
             return
         if verbose:

@@ -475,8 +475,9 @@ def load_tuned(path):
 
 
 def needs_layout(cfg):
-    """True if a configuration reads A in a way only some layouts allow."""
-    return bool(cfg.get("VA") or cfg.get("FL"))
+    """True if a configuration reads A in a way only some layouts allow
+    (paired loads, slab reads, direct loads of whole stages into LDS)."""
+    return bool(cfg.get("VA") or cfg.get("FL") or cfg.get("kind") == "lds")
 
 
 def exact_variants(widths, tuned=None):

@@ -58,6 +58,31 @@ fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double
     }
 }
 
+// Reduction ablation only (never the default): every block's partial is
+// added into C with global FP64 atomics, as the paper's global-atomic variant
+// does (Section 3.2); C is cleared first.  Thread (b, e) adds slot b, entry e;
+// the order of the additions, and so the rounding, varies from run to run.
+template <int CW>
+__global__ void __launch_bounds__(256)
+atomic_partials(const double* __restrict__ ws, int G, int E, int N, double* __restrict__ C, int64_t ldc)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)G * E) return;
+    const int b = (int)(i / E), e = (int)(i - (int64_t)b * E);
+    const int q = e / CW;
+    const int m = q / N, n = q - m * N;
+    atomicAdd(C + ((int64_t)m * ldc + n) * CW + (e - q * CW), ws[(size_t)b * E + e]);
+}
+
+__global__ void __launch_bounds__(256) clear_small(double* __restrict__ C, int M, int N, int CW, int64_t ldc)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * N * CW) return;
+    const int q = i / CW;
+    const int m = q / N, n = q - m * N;
+    C[((int64_t)m * ldc + n) * CW + (i - q * CW)] = 0.0;
+}
+
 // Fixed scratch of tsg_tsmttsm_noalloc: the per-block partial sums of one
 // launch (a slot of M N (x2 complex) doubles per block).  Every device the
 // library runs on holds its own copy for the life of the process.  In host
@@ -73,6 +98,7 @@ namespace {
 thread_local std::string g_err;
 thread_local std::string g_force;  // variant forced by tsg_force_variant ("" = automatic choice)
 thread_local int g_grid_cap = 0;   // block cap set by tsg_set_grid_limit (0 = none)
+thread_local int g_reduction = 0;  // cross-block reduction set by tsg_set_reduction (0 = fixed-order fold)
 
 tsg_status fail(tsg_status s, const char* fmt, ...)
 {
@@ -391,6 +417,23 @@ tsg_status tsmttsm_call(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N
     v->launch(p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(TSG_E_HIP, "launch of %s: %s", v->name, hipGetErrorString(e));
+    if (p.grid > 1 && g_reduction == TSG_REDUCE_ATOMIC) {
+        const int cw = is_complex(dt) ? 2 : 1;
+        const int E = M * N * cw;
+        double* Cd = static_cast<double*>(C);
+        hipLaunchKernelGGL(tsg::clear_small, dim3((E + 255) / 256), dim3(256), 0, p.stream, Cd, M, N, cw, ldc);
+        const int64_t n = (int64_t)p.grid * E;
+        if (cw == 2)
+            hipLaunchKernelGGL((tsg::atomic_partials<2>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p.stream,
+                               p.ws, p.grid, E, N, Cd, ldc);
+        else
+            hipLaunchKernelGGL((tsg::atomic_partials<1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p.stream,
+                               p.ws, p.grid, E, N, Cd, ldc);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail(TSG_E_HIP, "launch of the atomic reduction: %s", hipGetErrorString(e));
+        return TSG_OK;
+    }
+    if (p.grid > 1 && g_reduction == TSG_REDUCE_NONE) return TSG_OK;  // ablation: partials left in the workspace
     if (p.grid > 1 && (e = launch_fold(p, is_complex(dt))) != hipSuccess)
         return fail(TSG_E_HIP, "launch of the partial fold: %s", hipGetErrorString(e));
     return TSG_OK;
@@ -572,6 +615,14 @@ tsg_status tsg_set_grid_limit(int32_t blocks)
     g_err.clear();
     if (blocks < 0) return fail(TSG_E_ARG, "grid limit %d < 0", blocks);
     g_grid_cap = blocks;
+    return TSG_OK;
+}
+
+tsg_status tsg_set_reduction(int32_t mode)
+{
+    if (mode != TSG_REDUCE_FOLD && mode != TSG_REDUCE_ATOMIC && mode != TSG_REDUCE_NONE)
+        return fail(TSG_E_ARG, "unknown reduction mode %d", (int)mode);
+    g_reduction = mode;
     return TSG_OK;
 }
 

@@ -49,15 +49,43 @@ def _widths(name):
 
 
 def cmd_build(args):
+    """Compile the candidates of the selected widths, operations and dtypes
+    into a tuning library.  --kinds keeps only candidates of those mappings
+    (plus, with --with-tuned, each width's configuration in the current
+    table, so that a partial search re-times the incumbent beside them);
+    --tag builds a library of its own (libtsgemm_<tag>.so, for
+    TSG_LIBRARY) without touching the default tuning library."""
     sys.path.insert(0, ROOT)
     from paper_1905_03136_amd import build, codegen
     variants = codegen.tuning_variants(_widths(args.widths))
     ops = set(args.ops.split(",")) if args.ops else None
     dtypes = set(args.dtypes.split(",")) if args.dtypes else None
-    # exact-width candidates of the selected operations and dtypes (run-time-width variants always)
-    variants = [v for v in variants if v["M"] == 0 or
-                ((not ops or v["op"] in ops) and (not dtypes or v["dt"] in dtypes))]
-    build.build(variants=variants, lib_path=TUNE_LIB, tag="_tune")
+    kinds = set(args.kinds.split(",")) if args.kinds else None
+    tuned = codegen.load_tuned(os.path.join(HERE, "tuned.json")) if args.with_tuned else {}
+
+    def keep(v):
+        if v["M"] == 0:
+            return True  # run-time-width variants always
+        if (ops and v["op"] not in ops) or (dtypes and v["dt"] not in dtypes):
+            return False
+        if kinds is None or v["cfg"]["kind"] in kinds:
+            return True
+        return tuned.get((v["op"], v["dt"], v["M"], v["N"])) == v["cfg"]
+    variants = [v for v in variants if keep(v)]
+    names = {codegen.variant_name(v) for v in variants}
+    # the incumbent of a width need not be among the enumerated candidates
+    for key, cfg in tuned.items():
+        if len(key) != 4:
+            continue
+        op, dt, M, N = key
+        if (ops and op not in ops) or (dtypes and dt not in dtypes) or (M, N) not in _widths(args.widths):
+            continue
+        v = dict(op=op, dt=dt, M=M, N=N, maxM=M, maxN=N, cfg=cfg)
+        if codegen.variant_name(v) not in names:
+            names.add(codegen.variant_name(v))
+            variants.append(v)
+    lib = TUNE_LIB if not args.tag else os.path.join(HERE, "libtsgemm_%s.so" % args.tag)
+    build.build(variants=variants, lib_path=lib, tag="_" + (args.tag or "tune"))
 
 
 def exact_product(op, A, B):
@@ -385,6 +413,69 @@ def ablation(db_paths, ops=None):
     return rows
 
 
+def heatmap(db_paths, op, dt, M, N, resources=None):
+    """The tile-size cross section of the search at one width (the paper's
+    tile heat map with register iso-lines, Section 5.2): for each tile of a
+    wave (mapping and its block grid) and each number of rows in flight U,
+    the fastest correct configuration (over the other dimensions) with its
+    time and the registers its kernel uses (VGPR + AGPR, from the build's
+    resource records).  Returns (tiles, Us, cells) with cells[(tile, U)] =
+    (us, name, regs)."""
+    recs = {}
+    for path in db_paths:
+        with open(path) as f:
+            for line in f:
+                try:
+                    r = json.loads(line)
+                except ValueError:
+                    continue
+                if (r.get("ok") and r.get("us") and r.get("op") == op and r.get("dt") == dt and r.get("M") == M
+                        and r.get("N") == N):
+                    recs[r["name"]] = r
+    cells = {}
+    for r in recs.values():
+        c = r["cfg"]
+        if c["kind"] in ("mfma", "a32") and op == "tsmttsm":
+            tile = "%s %dx%d blocks, %d-way split" % (c["kind"], c["MB"], c["NB"], c.get("MW", 1))
+        elif c["kind"] == "lds":
+            tile = "lds %dx%d blocks, %dx%d waves" % (c["MB"], c["NB"], c["WM"], c["WN"])
+        elif c["kind"] in ("mfma", "a32"):
+            tile = "%s %d slices x %d blocks" % (c["kind"], c["MS"], c["NB"])
+        elif c["kind"] == "valu":
+            tile = "valu %dx%d" % (c["MX"], c["NX"])
+        else:
+            tile = c["kind"]
+        u = c.get("U", c.get("RT", 0) // 4)
+        res = (resources or {}).get(r["name"])
+        regs = (res.get("vgpr", 0) + res.get("agpr", 0)) if res else None
+        key = (tile, u)
+        if key not in cells or r["us"] < cells[key][0]:
+            cells[key] = (r["us"], r["name"], regs)
+    tiles = sorted({k[0] for k in cells})
+    us = sorted({k[1] for k in cells})
+    return tiles, us, cells
+
+
+def cmd_heatmap(args):
+    from paper_1905_03136_amd import build, codegen
+    M, N = (int(x) for x in args.width.split("x"))
+    res = build.variant_resources([dict(op=args.op, dt=args.dt, M=M, N=N, maxM=M, maxN=N, cfg=c)
+                                   for c in codegen.candidates(args.op, args.dt, M, N)], tag="_" + args.tag)
+    tiles, us, cells = heatmap(args.db, args.op, args.dt, M, N, res)
+    best = min(v[0] for v in cells.values())
+    print("| tile of a wave \\ rows in flight (4-row steps) | " + " | ".join("U=%d" % u for u in us) + " |")
+    print("|---|" + "---:|" * len(us))
+    for t in tiles:
+        row = []
+        for u in us:
+            v = cells.get((t, u))
+            row.append("-" if not v else "%.2f (%s regs)" % (v[0] / best, v[2] if v[2] is not None else "?"))
+        print("| %s | %s |" % (t, " | ".join(row)))
+    print()
+    print("Entries: time relative to the fastest configuration of %s %s %dx%d (%.1f us), and the registers "
+          "(VGPR + AGPR per lane) of that kernel." % (args.op, args.dt, M, N, best))
+
+
 def cmd_ablate(args):
     rows = ablation(args.db, set(args.ops.split(",")) if args.ops else None)
     print("| op | real/complex | dimension | value | widths | slowdown (geo. mean) | slowdown (max) |")
@@ -400,6 +491,9 @@ def main(argv=None):
     b.add_argument("--widths", default="graded")
     b.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
     b.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
+    b.add_argument("--kinds", default="", help="comma-separated subset of the mappings (valu,packed,mfma,a32,lds)")
+    b.add_argument("--with-tuned", action="store_true", help="add each width's configuration in tuned.json")
+    b.add_argument("--tag", default="", help="build libtsgemm_<tag>.so apart from the default tuning library")
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
     r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
@@ -413,6 +507,12 @@ def main(argv=None):
     ab = sub.add_parser("ablate", help="cost of fixing each design dimension, from tuning databases")
     ab.add_argument("--db", action="append", required=True, help="a tuning database (repeatable; later ones win)")
     ab.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
+    hm = sub.add_parser("heatmap", help="tile x rows-in-flight cross section of the search at one width")
+    hm.add_argument("--db", action="append", required=True)
+    hm.add_argument("--op", default="tsmttsm")
+    hm.add_argument("--dt", default="r64")
+    hm.add_argument("--width", default="32x32")
+    hm.add_argument("--tag", default="tune", help="build whose resource records give the register counts")
     bt = sub.add_parser("batched", help="GPU: input bytes per slab and queue interleave of the batched form")
     bt.add_argument("--count", type=int, default=64)
     bt.add_argument("--item-bytes", default="1048576,2097152,4194304,8388608,16777216")
@@ -434,6 +534,8 @@ def main(argv=None):
         cmd_ablate(a)
     elif a.cmd == "batched":
         cmd_batched(a)
+    elif a.cmd == "heatmap":
+        cmd_heatmap(a)
     else:
         write_table(a.db, a.out, a.merge)
 

@@ -193,3 +193,11 @@ def test_orth_batched_host_validation(lib):
     assert _lib.tsg_orth_batched(A + 8, 2, A + 8, n, None) == _lib.TSG_E_ARG   # workspace not 256-aligned
     assert _lib.tsg_orth_batched(A, 2, A, 64, None) == _lib.TSG_E_ARG          # below the queue's own size
     assert _lib.tsg_orth_batched_check(None) == _lib.TSG_E_ARG
+
+
+def test_reduction_hook_rejects_unknown_modes(lib):
+    """Host-side validation of the reduction ablation hook (no GPU needed)."""
+    from paper_1905_03136_amd import _lib
+    assert _lib.tsg_set_reduction(7) == _lib.TSG_E_ARG
+    assert _lib.tsg_set_reduction(-1) == _lib.TSG_E_ARG
+    assert _lib.tsg_set_reduction(_lib.TSG_REDUCE_FOLD) == _lib.TSG_OK
