@@ -70,7 +70,7 @@ def _resources(remarks):
     hipcc's resource-usage remarks."""
     out, cur = {}, None
     keys = {"VGPRs": "vgpr", "AGPRs": "agpr", "ScratchSize [bytes/lane]": "scratch",
-            "Occupancy [waves/SIMD]": "occupancy"}
+            "Occupancy [waves/SIMD]": "occupancy", "LDS Size [bytes/block]": "lds"}
     for line in remarks.splitlines():
         m = re.search(r"Function Name: (\S+)", line)
         if m:

@@ -157,6 +157,15 @@ def cmd_run(args):
         tdt = torch.complex128 if cplx else torch.float64            # small matrix C
         sdt = (torch.complex64 if cplx else torch.float32) if f32 else tdt  # storage of A, B
         cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
+        if args.prune:
+            # the performance model drops candidates predicted far slower than
+            # the best prediction (register use from the tuning build's records)
+            from paper_1905_03136_amd import build, model
+            res = build.variant_resources(cands, tag="_" + args.prune_tag)
+            kept = model.prune(cands, K, res, args.prune)
+            print("[tune] %s %s %dx%d: model keeps %d of %d candidates" % (op, dt, M, N, len(kept), len(cands)),
+                  flush=True)
+            cands = kept
         if not cands:
             continue
         # integer-valued problem: every candidate must give the exact product
@@ -504,6 +513,9 @@ def main(argv=None):
     r.add_argument("--reps", type=int, default=5)
     r.add_argument("--warmup", type=int, default=2)
     r.add_argument("--merge", default="", help="keep the entries of this table the run does not cover")
+    r.add_argument("--prune", type=float, default=0.0,
+                   help="time only candidates the performance model predicts within this factor of the best")
+    r.add_argument("--prune-tag", default="tune", help="build whose resource records the model reads")
     ab = sub.add_parser("ablate", help="cost of fixing each design dimension, from tuning databases")
     ab.add_argument("--db", action="append", required=True, help="a tuning database (repeatable; later ones win)")
     ab.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
