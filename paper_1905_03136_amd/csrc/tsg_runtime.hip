@@ -19,17 +19,22 @@
 namespace tsg {
 
 // Sum of the G per-block partials of a TSMTTSM launch (slot b holds E doubles
-// at ws + b * E) into C, in a fixed order: each block takes EB consecutive
-// entries (EB a power of two <= 8) and S = 256 / EB slices; slice s sums slots
-// s, s + S, s + 2S, ... in increasing order (loads issued eight at a time, the
-// additions in slot order), and the slices are combined by a fixed pairwise
-// tree.  The result is bitwise reproducible for a given grid.
+// at ws + b * E) into C, in a fixed order: each block of kFoldThreads threads
+// takes EB consecutive entries (EB a power of two <= 8) and S = kFoldThreads /
+// EB slices; slice s sums slots s, s + S, s + 2S, ... in increasing order
+// (loads issued eight at a time, the additions in slot order), and the slices
+// are combined by a fixed pairwise tree.  The result is bitwise reproducible
+// for a given grid.  Wide blocks keep the chain of dependent loads of a
+// thread short (G <= 2048 slots: at most two batches of eight), which is what
+// the fold's time is made of at small K.
+constexpr int kFoldThreads = 1024;
+
 template <int CW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFoldThreads)
 fold_partials(const double* __restrict__ ws, int G, int E, int EB, int N, double* __restrict__ C, int64_t ldc)
 {
-    __shared__ double red[256];
-    const int S = 256 / EB;
+    __shared__ double red[kFoldThreads];
+    const int S = kFoldThreads / EB;
     const int el = threadIdx.x & (EB - 1);
     const int s = threadIdx.x / EB;
     const int e = blockIdx.x * EB + el;
@@ -366,11 +371,11 @@ hipError_t launch_fold(const tsg::Launch& p, bool cplx)
     while (eb < E && eb < 8) eb <<= 1;
     const int blocks = (E + eb - 1) / eb;
     if (cplx)
-        hipLaunchKernelGGL((tsg::fold_partials<2>), dim3(blocks), dim3(256), 0, p.stream, p.ws, p.grid, E, eb, p.N,
-                           static_cast<double*>(p.Y), p.ldy);
+        hipLaunchKernelGGL((tsg::fold_partials<2>), dim3(blocks), dim3(tsg::kFoldThreads), 0, p.stream, p.ws, p.grid,
+                           E, eb, p.N, static_cast<double*>(p.Y), p.ldy);
     else
-        hipLaunchKernelGGL((tsg::fold_partials<1>), dim3(blocks), dim3(256), 0, p.stream, p.ws, p.grid, E, eb, p.N,
-                           static_cast<double*>(p.Y), p.ldy);
+        hipLaunchKernelGGL((tsg::fold_partials<1>), dim3(blocks), dim3(tsg::kFoldThreads), 0, p.stream, p.ws, p.grid,
+                           E, eb, p.N, static_cast<double*>(p.Y), p.ldy);
     return hipGetLastError();
 }
 
