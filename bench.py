@@ -504,7 +504,7 @@ def cpu_baseline(K_sample):
             "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
 
 
-def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False):
+def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False, widths=tuple(range(1, 65))):
     """Every square width M = N = 1..64, D and Z, both products at K rows:
     median time of `reps` calls (one width at a time, exact-size operands)
     and the fraction of the spec roofline; one JSON line per width, then a
@@ -515,7 +515,7 @@ def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False):
     paper's library comparison (Section 1.5), measured on this GPU."""
     rows = []
     for cplx in (False, True):
-        for w in range(1, 65):
+        for w in widths:
             A = inputs.device_uniform(K, w, w, inputs.STREAM_A, cplx, dev)
             B = inputs.device_uniform(K, w, w, inputs.STREAM_B, cplx, dev)
             X = inputs.device_uniform(w, w, w, inputs.STREAM_C, cplx, dev)
@@ -612,6 +612,7 @@ def main():
     ap.add_argument("--no-smi", action="store_true", help="do not query rocm-smi for clocks and power")
     ap.add_argument("--all-widths", action="store_true",
                     help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
+    ap.add_argument("--width-list", default="", help="with --all-widths: comma-separated square widths (default 1..64)")
     ap.add_argument("--reduction-sweep", action="store_true",
                     help="instead of the bench step: TSMTTSM reduction variants (fold / atomic / none) against K")
     ap.add_argument("--vendor", action="store_true",
@@ -628,7 +629,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if a.all_widths:
-        all_widths(torch, api, inputs, dev, vendor=a.vendor)
+        ws = tuple(int(x) for x in a.width_list.split(",")) if a.width_list else tuple(range(1, 65))
+        all_widths(torch, api, inputs, dev, vendor=a.vendor, widths=ws)
         return
     if a.reduction_sweep:
         reduction_sweep(torch, api, inputs, dev)

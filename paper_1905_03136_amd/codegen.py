@@ -36,8 +36,9 @@ SQUARE_ALL = [(w, w) for w in range(1, 65)]
 # pre-generated widths of the precision form (others use run-time-width variants)
 PRECISION = GRADED
 # widths whose every candidate the default build compiles into the tuning
-# library (the sweep widths and two odd pairs with guards on every tile)
-TUNE_WIDTHS = GRADED + [(3, 5), (13, 7)]
+# library (the sweep widths and odd pairs with guards on every tile; 17 x 33
+# also reaches the LDS-staged kernels with odd complex widths)
+TUNE_WIDTHS = GRADED + [(3, 5), (13, 7), (17, 33)]
 
 
 def is_f32(dt):
@@ -101,7 +102,11 @@ def _lds_candidates(op, dt, M, N):
         return out
     cplx = DTYPES[dt][1]
     cw = 2 if cplx else 1
-    if M * cw < 2 or N * cw < 2:
+    # Real odd widths: with K M odd the last element of A shares its 16-byte
+    # load with the 8 bytes past the end, and the clamp that keeps that load
+    # inside the matrix would move the element (the autotuner's exact-product
+    # gate rejected these kernels); complex elements are 16 bytes each.
+    if not cplx and (M % 2 or N % 2):
         return out
     mbt, nbt = _ceil(M, 16), _ceil(N, 16)
     for wm in (1, 2, 4, 8):

@@ -529,9 +529,11 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // row of the stage, each element of A and B crosses HBM once.
 //
 // Needs lda = M and ldb = N (a stage is one contiguous run of A and one of
-// B) and 16-byte aligned A and B.  Lane addresses past the end of a matrix
-// are clamped to its last 16 bytes; the rows they fill (past K) are zeroed
-// when read from LDS.
+// B), 16-byte aligned A and B, and an even number of doubles in each of A
+// and B (complex data, or even real widths): lane addresses past the end of
+// a matrix are clamped to its last 16 bytes, which then hold only elements
+// of rows past K, zeroed when read from LDS.  (With an odd count the last
+// element would share its 16 bytes with the end and be moved by the clamp.)
 // ============================================================================
 
 // One wave-wide direct load: 64 lanes x 16 bytes from src + 2 lane (doubles)
@@ -554,6 +556,7 @@ tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     static_assert(MC > 0 && NC > 0 && RT % 4 == 0 && RT % 2 == 0, "compile-time widths, stages of 4-row steps");
     static_assert(WM * MB * 16 >= MC && WN * NB * 16 >= NC, "the waves' blocks cover C");
     static_assert(CPLX || !G3, "the three-product form is for complex data");
+    static_assert(CPLX || (MC % 2 == 0 && NC % 2 == 0), "an even number of doubles in A and B (see above)");
     constexpr int SA = ((RT * MC * CW + 127) / 128) * 128;       // doubles of A per stage (whole 1 KB loads)
     constexpr int SB = ((RT * NC * CW + 127) / 128) * 128;
     constexpr int SS = SA + SB;                                   // one stage
