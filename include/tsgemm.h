@@ -136,9 +136,10 @@ tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
  *  - Its device address is resolved once per device, by tsg_init(device) or
  *    by the first call on that device; neither allocates.
  *  - A call whose partial sums would exceed the 32 MiB returns
- *    TSG_E_UNSUPPORTED and enqueues nothing.  (Every shape of the supported
- *    range needs at most 2048 blocks x M N (x2 complex) doubles on a grid
- *    sized by occupancy; the largest, complex 64 x 64, 16 to 32 MiB.)
+ *    TSG_E_UNSUPPORTED and enqueues nothing.  (The library sizes
+ *    every TSMTTSM grid so that its partial sums, one slot of M N (x2
+ *    complex) doubles per block, fit in the 32 MiB, so no shape of the
+ *    supported range is refused.)
  *  - Every call on one device shares that device's scratch and leaves its
  *    partial sums there: calls that overlap in time on one device (different
  *    streams, or host threads) race and give wrong results.  Order them on

@@ -353,6 +353,14 @@ int grid_for(int dev, const tsg::Variant& v, int64_t K, int M, int N, int cus)
     const int64_t tiles = (K + rows - 1) / rows;
     const int64_t cap = (int64_t)cus * occupancy(dev, v);
     int64_t g = tiles < cap ? tiles : cap;
+    if (v.op == tsg::OP_TSMTTSM) {
+        // the per-block partial sums of a launch always fit the no-alloc
+        // scratch, so both TSMTTSM entry points run the same grid (and give
+        // the same bits) for every shape
+        const int64_t E = (int64_t)M * N * (is_complex((tsg_dtype)v.dt) ? 2 : 1);
+        const int64_t gmax = (int64_t)(tsg::kScratchBytes / (E * sizeof(double)));
+        if (g > gmax) g = gmax;
+    }
     if (g_grid_cap > 0 && g > g_grid_cap) g = g_grid_cap;
     return g < 1 ? 1 : (int)g;
 }
