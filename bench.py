@@ -20,6 +20,7 @@ autograd form (K = 2^22, M = N = 32).
     python bench.py --all-widths      # every square width 1..64 instead (one JSON line each)
     python bench.py --all-widths --vendor   # ... with torch.matmul (rocBLAS / hipBLASLt) beside each
     python bench.py --reduction-sweep       # TSMTTSM reduction variants against K (ablation)
+    python bench.py --pair-sweep            # nonsymmetric (M, N) grid
 """
 import argparse
 import json
@@ -550,6 +551,38 @@ def all_widths(torch, api, inputs, dev, K=K_SWEEP, reps=3, vendor=False, widths=
     print(json.dumps({"all_widths_summary": summary}), flush=True)
 
 
+def pair_sweep(torch, api, inputs, dev, widths=(1, 4, 8, 16, 24, 32, 40, 48, 56, 64), K=K_SWEEP, reps=3):
+    """Nonsymmetric widths: every (M, N) with M and N in `widths`, D and Z, both
+    products at K rows (the paper measures only M = N and calls the other
+    shapes "not fundamentally different", Section 1.3).  One JSON line per
+    pair, then a summary with the mean and minimum fraction of the spec
+    roofline per (dtype, operation) and how many pairs reach 0.8."""
+    rows = []
+    for cplx in (False, True):
+        for M in widths:
+            for N in widths:
+                A = inputs.device_uniform(K, M, M, inputs.STREAM_A, cplx, dev)
+                B = inputs.device_uniform(K, N, N, inputs.STREAM_B, cplx, dev)
+                X = inputs.device_uniform(M, N, M + N, inputs.STREAM_C, cplx, dev)
+                Co = torch.empty((M, N), dtype=A.dtype, device=dev)
+                rec = {"dtype": "Z" if cplx else "D", "M": M, "N": N, "K": K}
+                for op, fn in (("tsmttsm", lambda: api.tsmttsm(A, B, out=Co)), ("tsmm", lambda: api.tsmm(A, X, out=B))):
+                    t = time_call(torch, fn, reps=reps, warmup=1)
+                    byts, flops = algorithmic(op, cplx, K, M, N)
+                    rec[op] = {"us": round(t * 1e6, 1), "roof_frac": round(roofline_time(byts, flops) / t, 4),
+                               "kernel": api.kernel_name(op, A.dtype, M, N)}
+                print(json.dumps(rec), flush=True)
+                rows.append(rec)
+                del A, B, X, Co
+    summary = {}
+    for dt in ("D", "Z"):
+        for op in ("tsmttsm", "tsmm"):
+            f = [r[op]["roof_frac"] for r in rows if r["dtype"] == dt]
+            summary["%s_%s" % (dt, op)] = {"mean": round(sum(f) / len(f), 4), "min": min(f),
+                                           "pairs": len(f), "at_least_0.8": sum(1 for x in f if x >= 0.8)}
+    print(json.dumps({"pair_sweep_summary": summary}), flush=True)
+
+
 def reduction_sweep(torch, api, inputs, dev, widths=(4, 32), Ks=(10**3, 10**4, 10**5, 10**6, 10**7, 10**8),
                     reps=20):
     """Ablation of TSMTTSM's cross-block reduction against K (the paper's
@@ -613,6 +646,8 @@ def main():
     ap.add_argument("--all-widths", action="store_true",
                     help="instead of the bench step: every square width 1..64 (D, Z, both products), one JSON line each")
     ap.add_argument("--width-list", default="", help="with --all-widths: comma-separated square widths (default 1..64)")
+    ap.add_argument("--pair-sweep", action="store_true",
+                    help="instead of the bench step: nonsymmetric (M, N) grid, D and Z, both products")
     ap.add_argument("--reduction-sweep", action="store_true",
                     help="instead of the bench step: TSMTTSM reduction variants (fold / atomic / none) against K")
     ap.add_argument("--vendor", action="store_true",
@@ -634,6 +669,9 @@ def main():
         return
     if a.reduction_sweep:
         reduction_sweep(torch, api, inputs, dev)
+        return
+    if a.pair_sweep:
+        pair_sweep(torch, api, inputs, dev)
         return
     print("[bench] allocating and generating inputs", file=sys.stderr, flush=True)
     K = K_SWEEP

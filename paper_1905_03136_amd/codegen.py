@@ -109,9 +109,10 @@ def _lds_candidates(op, dt, M, N):
     if not cplx and (M % 2 or N % 2):
         return out
     mbt, nbt = _ceil(M, 16), _ceil(N, 16)
-    for wm in (1, 2, 4, 8):
-        for wn in (1, 2, 4, 8):
-            if wm * wn not in (2, 4, 8) or wm > mbt or wn > nbt:
+    for wm in range(1, 9):
+        for wn in range(1, 9):
+            wpb = wm * wn
+            if wpb < 2 or wpb > 8 or wm > mbt or wn > nbt:
                 continue
             mb, nb = _ceil(mbt, wm), _ceil(nbt, wn)
             if (wm - 1) * mb >= mbt or (wn - 1) * nb >= nbt:
@@ -122,17 +123,19 @@ def _lds_candidates(op, dt, M, N):
                     continue
                 for rt in (16, 32, 64):
                     ops = (rt // 4) * (mb + nb) * cw
-                    if acc + ops > 104:
-                        continue
                     stage = 2 * (_ceil(rt * M * cw, 128) + _ceil(rt * N * cw, 128)) * 128 * 8
                     lds = max(stage, M * N * cw * 8)
                     if lds > LDS_BYTES:
                         continue
-                    for occ in (1, 2, 4):
-                        # at most two waves per SIMD: the stage operands need the registers
-                        if occ > 1 and (occ * wm * wn > 8 or occ * lds > LDS_BYTES):
+                    for occ in (1, 2, 3, 4):
+                        waves = occ * wpb
+                        # the waves of a CU spread evenly over its four SIMDs, at most
+                        # three per SIMD, and the register model fits that many
+                        if waves % 4 or waves > 12 or occ * lds > LDS_BYTES:
                             continue
-                        c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wm * wn)
+                        if acc + ops > (104 if waves <= 8 else 80):
+                            continue
+                        c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wpb)
                         if occ > 1:
                             c["OCC"] = occ
                         if g3:
