@@ -583,6 +583,39 @@ def pair_sweep(torch, api, inputs, dev, widths=(1, 4, 8, 16, 24, 32, 40, 48, 56,
     print(json.dumps({"pair_sweep_summary": summary}), flush=True)
 
 
+def pair_table(path):
+    """Markdown tables (fraction of the roofline, rows M, columns N) of the
+    JSON lines a --pair-sweep run printed, one table per dtype and product,
+    followed by the summary line."""
+    rows, summary = [], None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line.startswith("{"):
+                continue
+            r = json.loads(line)
+            if "pair_sweep_summary" in r:
+                summary = r
+            else:
+                rows.append(r)
+    Ms = sorted({r["M"] for r in rows})
+    Ns = sorted({r["N"] for r in rows})
+    out = []
+    for dt in ("D", "Z"):
+        for op in ("tsmttsm", "tsmm"):
+            cell = {(r["M"], r["N"]): r[op]["roof_frac"] for r in rows if r["dtype"] == dt}
+            out.append("**%s %s** (rows M, columns N)\n" % (dt, op.upper()))
+            out.append("| M \\\\ N | " + " | ".join(str(n) for n in Ns) + " |")
+            out.append("|---|" + "---:|" * len(Ns))
+            for m in Ms:
+                out.append("| %d | " % m + " | ".join("%.2f" % cell[m, n] if (m, n) in cell else "" for n in Ns)
+                           + " |")
+            out.append("")
+    if summary:
+        out.append("```json\n%s\n```" % json.dumps(summary, indent=1))
+    return "\n".join(out)
+
+
 def reduction_sweep(torch, api, inputs, dev, widths=(4, 32), Ks=(10**3, 10**4, 10**5, 10**6, 10**7, 10**8),
                     reps=20):
     """Ablation of TSMTTSM's cross-block reduction against K (the paper's
@@ -648,11 +681,16 @@ def main():
     ap.add_argument("--width-list", default="", help="with --all-widths: comma-separated square widths (default 1..64)")
     ap.add_argument("--pair-sweep", action="store_true",
                     help="instead of the bench step: nonsymmetric (M, N) grid, D and Z, both products")
+    ap.add_argument("--pair-table", default="",
+                    help="no GPU: print the markdown tables of a --pair-sweep run's JSON lines (file) and exit")
     ap.add_argument("--reduction-sweep", action="store_true",
                     help="instead of the bench step: TSMTTSM reduction variants (fold / atomic / none) against K")
     ap.add_argument("--vendor", action="store_true",
                     help="with --all-widths: also time torch.matmul (rocBLAS / hipBLASLt) on the same operands")
     a = ap.parse_args()
+    if a.pair_table:
+        print(pair_table(a.pair_table))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "
               "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)

@@ -29,13 +29,29 @@ CFLAGS = [
     # keep the compiler from forming packed FP32 instructions (not used here anyway)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
-    "-I" + os.path.join(ROOT, "include"),
+    "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 
 # headers every unit includes; the C ABI header only the hand-written units
 HEADERS = [os.path.join(CSRC, h) for h in ("tsg_device.hpp", "tsg_kernels.hpp", "tsg_registry.hpp")]
 ABI_HEADER = os.path.join(ROOT, "include", "tsgemm.h")
 TUNE_LIB = os.path.join(HERE, "libtsgemm_tune.so")
+# builds of other variant sets (the autotuner's libraries): generated sources
+# and objects under <repository>/_build/<tag>/, out of the package
+TAGGED = os.path.join(ROOT, "_build")
+
+
+def build_dirs(tag):
+    """(generated sources, objects) of the build called ``tag`` ("" = the product)."""
+    if not tag:
+        return GEN, OBJ
+    t = tag.lstrip("_")
+    return os.path.join(TAGGED, t, "gen"), os.path.join(TAGGED, t, "obj")
+
+
+def tagged_lib(tag):
+    """Path of a named autotuning library (``tune build --tag``)."""
+    return os.path.join(TAGGED, "libtsgemm_%s.so" % tag.lstrip("_"))
 
 
 def _stale(obj, deps):
@@ -108,7 +124,7 @@ def variant_resources(variants, tag="_tune"):
     import json
     from paper_1905_03136_amd import codegen
     mangled = {}
-    for f in glob.glob(os.path.join(OBJ + tag, "*" + RESOURCES)):
+    for f in glob.glob(os.path.join(build_dirs(tag)[1], "*" + RESOURCES)):
         with open(f) as fh:
             mangled.update(json.load(fh))
     if not mangled:
@@ -159,8 +175,7 @@ def build(widths=None, jobs=None, extra_flags=(), verbose=True, variants=None, l
     """Generate and compile.  ``variants`` replaces the product's variant set
     (the autotuner builds all candidates this way into its own library,
     objects and generated sources kept apart by ``tag``)."""
-    gen_dir = GEN + tag
-    obj_dir = OBJ + tag
+    gen_dir, obj_dir = build_dirs(tag)
     srcs, variants = generate(widths, variants, gen_dir)
     table = os.path.join(gen_dir, "tsg_table.hip")
     units = [s for s in srcs if s != table]

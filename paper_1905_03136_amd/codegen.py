@@ -192,6 +192,66 @@ def _a32_candidates(op, dt, M, N):
     return out
 
 
+def _mfma_blocks(mbt, nb, cplx, nbufs=(2, 3, 4), occ=True):
+    """Matrix-core TSMTTSM configurations for a grid of mbt x nb 16 x 16
+    blocks of C (shared by the exact-width and run-time-width variants)."""
+    cw = 2 if cplx else 1
+    out = []
+    for mw in (1, 2, 3, 4):
+        if (mbt % mw and mw > 1) or mw > mbt:
+            continue
+        mb = _ceil(mbt, mw)
+        acc = mb * nb * 4 * cw
+        # three m-slices (widths 33..48) need blocks of a multiple of three waves
+        for w in ((6, 12) if mw == 3 else (4, 8)):
+            # 256-thread blocks may use the whole register file of one
+            # wave per SIMD: room for the 3 x 3 complex block grid
+            # (widths 33..48), which no wave split divides
+            if w % mw or acc > (72 if w == 4 else 64):
+                continue
+            for u in (1, 2, 4):
+                for nbuf in nbufs:
+                    ops = nbuf * u * (mb + nb) * cw
+                    if ops > 72 or (nbuf > 2 and u > 2):
+                        continue
+                    # two waves per SIMD (OCC = 2, implied by 384- and
+                    # 512-thread blocks) leave each lane 256 registers in
+                    # all, three (768 threads) about 170
+                    two = acc + ops <= 104
+                    if (w > 4 and not two) or (w == 12 and acc + ops > 72):
+                        continue
+                    c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf)
+                    out.append(c)
+                    if occ and w == 4 and two and mw > 1:
+                        out.append(dict(c, OCC=2))
+                    # complex: Gauss's three-product form needs a third
+                    # accumulator set (half the size of the two it replaces)
+                    acc3 = mb * nb * 4 * 3
+                    if cplx and acc3 <= 64 and (w == 4 or acc3 + ops <= 104):
+                        out.append(dict(c, G3=1))
+    return out
+
+
+def _mfma_slices(ms, nb, cplx, va=False, nbufs=(2, 3, 4)):
+    """Matrix-core TSMM configurations for a contraction depth of ms 4-wide
+    slices and nb 16-column blocks of B (shared by the exact-width and
+    run-time-width variants); ``va`` adds the paired loads of A."""
+    cw = 2 if cplx else 1
+    out = []
+    for u in (1, 2, 4):
+        for w in (4, 8):
+            for nbuf in nbufs:
+                ops = nbuf * u * ms * cw + u * nb * 4 * cw
+                if ops <= (96 if w == 8 else 160) and (nbuf == 2 or u <= 2):
+                    if va:
+                        out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, VA=1))
+                    out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
+                    # complex three-product form: one more accumulator set, C staged three times
+                    if cplx and ops + u * nb * 4 <= (96 if w == 8 else 160):
+                        out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
+    return out
+
+
 def _candidates(op, dt, M, N):
     cw = 2 if DTYPES[dt][1] else 1
     cplx = DTYPES[dt][1]
@@ -210,39 +270,7 @@ def _candidates(op, dt, M, N):
                     out.append(dict(kind="valu", MX=M, NX=N, U=u, VA=int(not cplx and M % 2 == 0),
                                     VB=int(not cplx and N % 2 == 0), WPB=WPB))
         if M > 8 or N > 8:
-            mbt, nb = _ceil(M, 16), _ceil(N, 16)
-            for mw in (1, 2, 3, 4):
-                if (mbt % mw and mw > 1) or mw > mbt:
-                    continue
-                mb = _ceil(mbt, mw)
-                acc = mb * nb * 4 * cw
-                # three m-slices (widths 33..48) need blocks of a multiple of three waves
-                for w in ((6, 12) if mw == 3 else (4, 8)):
-                    # 256-thread blocks may use the whole register file of one
-                    # wave per SIMD: room for the 3 x 3 complex block grid
-                    # (widths 33..48), which no wave split divides
-                    if w % mw or acc > (72 if w == 4 else 64):
-                        continue
-                    for u in (1, 2, 4):
-                        for nbuf in (2, 3, 4):
-                            ops = nbuf * u * (mb + nb) * cw
-                            if ops > 72 or (nbuf > 2 and u > 2):
-                                continue
-                            # two waves per SIMD (OCC = 2, implied by 384- and
-                            # 512-thread blocks) leave each lane 256 registers in
-                            # all, three (768 threads) about 170
-                            two = acc + ops <= 104
-                            if (w > 4 and not two) or (w == 12 and acc + ops > 72):
-                                continue
-                            c = dict(kind="mfma", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf)
-                            out.append(c)
-                            if w == 4 and two and mw > 1:
-                                out.append(dict(c, OCC=2))
-                            # complex: Gauss's three-product form needs a third
-                            # accumulator set (half the size of the two it replaces)
-                            acc3 = mb * nb * 4 * 3
-                            if cplx and acc3 <= 64 and (w == 4 or acc3 + ops <= 104):
-                                out.append(dict(c, G3=1))
+            out += _mfma_blocks(_ceil(M, 16), _ceil(N, 16), cplx)
         # tails on the vector unit: full blocks on the matrix cores, the
         # M mod 16 rows and N mod 16 columns of C as FMAs (one wave per row group)
         rm, rn = M % 16, N % 16
@@ -307,17 +335,7 @@ def _candidates(op, dt, M, N):
     # vector and packed kernels stay ahead)
     if M >= 3 or N >= 16:
         ms, nb = _ceil(M, 4), _ceil(N, 16)
-        for u in (1, 2, 4):
-            for w in (4, 8):
-                for nbuf in (2, 3, 4):
-                    ops = nbuf * u * ms * cw + u * nb * 4 * cw
-                    if ops <= (96 if w == 8 else 160) and (nbuf == 2 or u <= 2):
-                        if not cplx and M % 8 == 0:
-                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, VA=1))
-                        out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
-                        # complex three-product form: one more accumulator set, C staged three times
-                        if cplx and ops + u * nb * 4 <= (96 if w == 8 else 160):
-                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
+        out += _mfma_slices(ms, nb, cplx, va=not cplx and M % 8 == 0)
         # slab reads of A (rows contiguous): the wave's 16 U rows as one run of
         # loads of up to 16 bytes per lane, redistributed through LDS
         if not cplx:
@@ -404,19 +422,127 @@ def _gen_tsmm_cfg(ms, nb, cplx):
     return (2 if (4 * ms * cw + 8 * nb * cw) <= 96 else 1), WPB
 
 
-def generic_variants():
+# Run-time-width classes, each listed before every class that contains it
+# (the runtime takes the first record that covers (M, N), so a pair runs on
+# its smallest covering class).  TSMTTSM: grids of (m, n) 16 x 16 blocks of
+# C up to 4 x 4 (1 x 1 is row packing's); TSMM: contraction depths of ms
+# 4-wide slices times n blocks of 16 columns of B.
+GEN_TSMTTSM_CLASSES = sorted(((a, b) for a in range(1, 5) for b in range(1, 5) if (a, b) != (1, 1)),
+                             key=lambda c: (c[0] * c[1], c))
+GEN_TSMM_MS = (1, 2, 3, 4, 6, 8, 10, 12, 14, 16)
+GEN_TSMM_CLASSES = sorted(((ms, nb) for ms in GEN_TSMM_MS for nb in range(1, 5)), key=lambda c: (c[0] * c[1], c))
+GEN_TUNED_DTYPES = ("r64", "c128")
+
+
+def generic_limits(op, cls):
+    """(maxM, maxN) a run-time-width class serves."""
+    return (16 * cls[0], 16 * cls[1]) if op == "tsmttsm" else (4 * cls[0], 16 * cls[1])
+
+
+def generic_capacity(op, cfg):
+    """(maxM, maxN) a matrix-core configuration can compute."""
+    if op == "tsmttsm":
+        return 16 * cfg["MB"] * cfg["MW"], 16 * cfg["NB"]
+    return 4 * cfg["MS"], 16 * cfg["NB"]
+
+
+def _next(values, x):
+    later = [v for v in values if v > x]
+    return later[0] if later else x
+
+
+def generic_candidates(op, dt, cls):
+    """Configurations the autotuner times for one run-time-width class: the
+    matrix-core kernels of the class's own grid and of the grids one step
+    larger in either dimension (padding a dimension can pay where a wider
+    grid fits the waves better)."""
+    cplx = DTYPES[dt][1]
+    out, seen = [], set()
+    if op == "tsmttsm":
+        a, b = cls
+        shapes = [(a, b), (_next((1, 2, 3, 4), a), b), (a, _next((1, 2, 3, 4), b))]
+        for sh in shapes:
+            for c in _mfma_blocks(sh[0], sh[1], cplx, nbufs=(2,), occ=False):
+                key = json.dumps(c, sort_keys=True)
+                if key not in seen:
+                    seen.add(key)
+                    out.append(c)
+    else:
+        ms, nb = cls
+        shapes = [(ms, nb), (_next(GEN_TSMM_MS, ms), nb), (ms, _next((1, 2, 3, 4), nb))]
+        for sh in shapes:
+            for c in _mfma_slices(sh[0], sh[1], cplx, nbufs=(2, 3)):
+                key = json.dumps(c, sort_keys=True)
+                if key not in seen:
+                    seen.add(key)
+                    out.append(c)
+    return out
+
+
+def generic_pairs(op, cls):
+    """Pairs (M, N) a run-time-width class is timed on: in each dimension the
+    smallest, middle and largest width the class serves as the tightest
+    class (combined so that no pair is square: squares have kernels of their
+    own)."""
+    def spans(lo_step, values, x):
+        prev = max([v for v in values if v < x], default=0)
+        lo, hi = lo_step * prev + 1, lo_step * x
+        return lo, (lo + hi) // 2, hi
+    if op == "tsmttsm":
+        m = spans(16, (1, 2, 3, 4), cls[0])
+    else:
+        m = spans(4, GEN_TSMM_MS, cls[0])
+    n = spans(16, (1, 2, 3, 4), cls[1])
+    pairs = [(m[0], n[1]), (m[1], n[2]), (m[2], n[0])]
+    return [(M, N) if M != N else (M, N - 1 if N > 1 else N + 1) for M, N in pairs]
+
+
+def tuned_generic(path=None):
+    """{(op, dt, maxM, maxN): cfg} of the run-time-width classes chosen by the
+    autotuner (tuned.json key "generic")."""
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for e in json.load(f).get("generic", []):
+                out[(e["op"], e["dt"], int(e["maxM"]), int(e["maxN"]))] = e["cfg"]
+    return out
+
+
+def _tsmm_rb(cfg, cplx):
+    """The twin of a TSMM run-time-width configuration that reads the old B
+    with A (calls with beta != 0): the depth and blocks of the beta = 0
+    kernel, rows in flight and waves by the register budget of the B ring."""
+    u, w = _gen_tsmm_cfg(cfg["MS"], cfg["NB"], cplx)
+    c = dict(kind="mfma", MS=cfg["MS"], NB=cfg["NB"], U=u, WPB=w, RB=1)
+    if cfg["MS"] >= 6:
+        c["WPB"] = WPB
+    return c
+
+
+def generic_variants(tuned_path=None):
     """Run-time-width variants: every (M, N) in [1, 64]^2 is served by one.
     The runtime takes the first one that covers (M, N), so each list runs
-    from the smallest covering shape to the largest."""
+    from the smallest covering shape to the largest.  The binary64 types
+    take the autotuned classes where the table has them."""
+    tuned = tuned_generic(tuned_path)
     out = []
     for dt, (_, cplx) in DTYPES.items():
         if is_a32(dt):
             continue  # served by the run-time-width variants of the binary64-arithmetic twin
-        cw = 2 if cplx else 1
         # TSMTTSM: row packing up to 16, then blocked matrix-core kernels
         out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16, maxN=16,
                         cfg=dict(kind="packed", U=4, WPB=WPB)))
+        auto = dt in GEN_TUNED_DTYPES and any(k[0] == "tsmttsm" and k[1] == dt for k in tuned)
+        if auto:
+            for cls in GEN_TSMTTSM_CLASSES:
+                mx, nx = generic_limits("tsmttsm", cls)
+                cfg = tuned.get(("tsmttsm", dt, mx, nx))
+                if cfg:
+                    out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=cfg))
         for (mbt, nb), cfgs in _GEN_TSMTTSM.items():
+            if auto and ("tsmttsm", dt, 16 * mbt, 16 * nb) in tuned:
+                continue
             mb, nbb, mw, u, w = cfgs[1 if cplx else 0]
             out.append(dict(op="tsmttsm", dt=dt, M=0, N=0, maxM=16 * mbt, maxN=16 * nb,
                             cfg=dict(kind="mfma", MB=mb, NB=nbb, MW=mw, U=u, WPB=w)))
@@ -429,18 +555,25 @@ def generic_variants():
         if not is_f32(dt):
             out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=2, maxN=2,
                             cfg=dict(kind="valu", MX=2, NX=2, U=2, VA=0, VB=0, WPB=WPB)))
-        shapes = [(1, 1), (2, 1)] + [(ms, nb) for ms in (4, 6, 8, 12, 16) for nb in (1, 2, 4)]
-        for ms, nb in shapes:
-            u, w = _gen_tsmm_cfg(ms, nb, cplx)
+        auto = dt in GEN_TUNED_DTYPES and any(k[0] == "tsmm" and k[1] == dt for k in tuned)
+        if auto:
+            tsmm = []
+            for cls in GEN_TSMM_CLASSES:
+                mx, nx = generic_limits("tsmm", cls)
+                cfg = tuned.get(("tsmm", dt, mx, nx))
+                if cfg:
+                    tsmm.append((mx, nx, cfg))
+        else:
+            tsmm = []
+            shapes = [(1, 1), (2, 1)] + [(ms, nb) for ms in (4, 6, 8, 12, 16) for nb in (1, 2, 4)]
+            for ms, nb in shapes:
+                u, w = _gen_tsmm_cfg(ms, nb, cplx)
+                tsmm.append((4 * ms, 16 * nb, dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)))
+        for mx, nx, cfg in tsmm:
             # a twin reading the old B with A serves calls with beta != 0 (its
             # register ring of B does not fit eight-wave blocks from 6 slices)
-            for rb in (1, 0):
-                cfg = dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)
-                if rb:
-                    cfg["RB"] = 1
-                    if ms >= 6:
-                        cfg["WPB"] = WPB
-                out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=4 * ms, maxN=16 * nb, cfg=cfg))
+            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=_tsmm_rb(cfg, cplx)))
+            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=cfg))
     return out
 
 
@@ -662,8 +795,8 @@ def emit(outdir, variants, per_file=6, exclude=(), batched=None):
     nfiles = max(1, math.ceil(len(variants) / per_file))
     for fi in range(nfiles):
         chunk = variants[fi * per_file:(fi + 1) * per_file]
-        body = ['// generated by codegen.py -- do not edit\n#include "../tsg_kernels.hpp"\n'
-                '#include "../tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
+        body = ['// generated by codegen.py -- do not edit\n#include "tsg_kernels.hpp"\n'
+                '#include "tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
         for k, v in enumerate(chunk):
             fn = "launch_%s" % variant_name(v)
             body.append(_launcher(v, fn))
@@ -675,7 +808,7 @@ def emit(outdir, variants, per_file=6, exclude=(), batched=None):
         path = os.path.join(outdir, "tsg_gen_%02d.hip" % fi)
         _write_if_changed(path, text)
         files.append(path)
-    table = ['// generated by codegen.py -- do not edit\n#include "../tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
+    table = ['// generated by codegen.py -- do not edit\n#include "tsg_registry.hpp"\n\nnamespace tsg_gen {\n']
     table.extend(decls)
     table.append("}  // namespace tsg_gen\n\n// host-only object: keep it out of the device compilation pass\n"
                  "#ifndef __HIP_DEVICE_COMPILE__\nnamespace tsg {\nusing namespace tsg_gen;\n"
@@ -714,7 +847,7 @@ def all_variants(widths=None, tuned_path=None):
         if (M, N) not in seen:
             seen.add((M, N))
             uniq.append((M, N))
-    return exact_variants(uniq, load_tuned(tuned_path)) + generic_variants()
+    return exact_variants(uniq, load_tuned(tuned_path)) + generic_variants(tuned_path)
 
 
 def template_of(v):

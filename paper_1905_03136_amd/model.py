@@ -39,7 +39,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# Measured on one MI355X (probes in bench.py / probes.py; the design doc lists the runs):
+# Measured on one MI355X (the probes of probes.py and the counters of the bench):
 # read bandwidth (GB/s) against bytes in flight per CU (256-thread blocks x
 # loads in flight x 16 B), Table-1 grid
 TABLE1 = [(4 << 10, 2350.0), (8 << 10, 3950.0), (16 << 10, 6200.0), (32 << 10, 7100.0), (64 << 10, 7050.0),

@@ -5,7 +5,7 @@ rates, and memory latency by pointer chasing (Section 1.6, Table 1; Section
 of the library (tsg_stream_probe, tsg_peak_probe, tsg_latency_probe); this
 module only allocates buffers, times the launches with events and prints.
 
-    python -m paper_1905_03136_amd.probes [--out gpurun_out/probes.json]
+    python -m paper_1905_03136_amd.probes [--out probes.json]
 """
 import argparse
 import json
@@ -140,7 +140,7 @@ def latency(sizes=(1 << 20, 64 << 20, 4 * GiB), steps=20000, stride_bytes=256):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/probes.json")
+    ap.add_argument("--out", default="probes.json")
     ap.add_argument("--gib", type=int, default=4, help="GiB streamed by the bandwidth probes")
     a = ap.parse_args(argv)
     import torch

@@ -53,10 +53,21 @@ def cmd_build(args):
     into a tuning library.  --kinds keeps only candidates of those mappings
     (plus, with --with-tuned, each width's configuration in the current
     table, so that a partial search re-times the incumbent beside them);
-    --tag builds a library of its own (libtsgemm_<tag>.so, for
+    --tag builds a library of its own (_build/libtsgemm_<tag>.so, for
     TSG_LIBRARY) without touching the default tuning library."""
     sys.path.insert(0, ROOT)
     from paper_1905_03136_amd import build, codegen
+    lib = TUNE_LIB if not args.tag else build.tagged_lib(args.tag)
+    if args.generic:
+        # the run-time-width classes' candidates (plus the product's own
+        # run-time-width variants, so that every pair has a kernel)
+        variants, names = [], set()
+        for v in generic_tuning_variants() + codegen.generic_variants():
+            if codegen.variant_name(v) not in names:
+                names.add(codegen.variant_name(v))
+                variants.append(v)
+        build.build(variants=variants, lib_path=lib, tag="_" + (args.tag or "tune"))
+        return
     variants = codegen.tuning_variants(_widths(args.widths))
     ops = set(args.ops.split(",")) if args.ops else None
     dtypes = set(args.dtypes.split(",")) if args.dtypes else None
@@ -84,7 +95,6 @@ def cmd_build(args):
         if codegen.variant_name(v) not in names:
             names.add(codegen.variant_name(v))
             variants.append(v)
-    lib = TUNE_LIB if not args.tag else os.path.join(HERE, "libtsgemm_%s.so" % args.tag)
     build.build(variants=variants, lib_path=lib, tag="_" + (args.tag or "tune"))
 
 
@@ -110,64 +120,38 @@ def _algorithmic(op, cplx, K, M, N, real_bytes=8):
     return s * (K * M + K * N) + c * M * N, (8 if cplx else 2) * M * N * K
 
 
-def cmd_run(args):
-    os.environ.setdefault("TSG_LIBRARY", TUNE_LIB)
-    sys.path.insert(0, ROOT)
-    import torch
+class _Timer:
+    """Forced variants timed on one (op, dtype, M, N) at K rows: each must
+    give the exact product of an integer-valued problem (on the full grid and
+    on three blocks), then the median of ``reps`` calls, rotating over buffer
+    sets of at least 1 GiB in all so that no call finds its operands in the
+    caches."""
 
-    from paper_1905_03136_amd import _lib, api, codegen, inputs
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    K = args.K
-    widths = _widths(args.widths)
-    groups = {}
-    for v in codegen.tuning_variants(widths):
-        if v["M"] == 0:
-            continue
-        groups.setdefault((v["op"], v["dt"], v["M"], v["N"]), []).append(v)
-    done = {}
-    if os.path.exists(args.db):
-        with open(args.db) as f:
-            for line in f:
-                try:
-                    r = json.loads(line)
-                    done[r["name"]] = r
-                except ValueError:
-                    pass
-    names = {_lib.tsg_variant_name(i) for i in range(_lib.tsg_variant_count())}
-    pool_elems = 2 * K * 64
-    pools = {}
-    for cplx in (False, True):
-        t = torch.empty(pool_elems * (2 if cplx else 1), dtype=torch.float64, device=dev)
-        g = torch.Generator(device=dev)
-        g.manual_seed(1234 + int(cplx))
-        t.uniform_(-1.0, 1.0, generator=g)
-        pools[cplx] = t
-    db = open(args.db, "a")
-    t_start = time.time()
-    dtypes = set(args.dtypes.split(",")) if args.dtypes else None
-    ops = set(args.ops.split(",")) if args.ops else None
-    for key in sorted(groups, key=lambda k: (k[0], k[1], k[2] * k[3])):
-        op, dt, M, N = key
-        if (dtypes and dt not in dtypes) or (ops and op not in ops):
-            continue
+    def __init__(self, K, warmup, reps):
+        import torch
+        from paper_1905_03136_amd import _lib
+        self.torch, self.K, self.warmup, self.reps = torch, K, warmup, reps
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+        self.names = {_lib.tsg_variant_name(i) for i in range(_lib.tsg_variant_count())}
+        self.pools = {}
+        for cplx in (False, True):
+            t = torch.empty(2 * K * 64 * (2 if cplx else 1), dtype=torch.float64, device=self.dev)
+            g = torch.Generator(device=self.dev)
+            g.manual_seed(1234 + int(cplx))
+            t.uniform_(-1.0, 1.0, generator=g)
+            self.pools[cplx] = t
+
+    def measure(self, op, dt, M, N, variants, base=None):
+        """One record per variant (``base`` merged into each)."""
+        torch = self.torch
+        from paper_1905_03136_amd import _lib, api, codegen, inputs
+        K, dev = self.K, self.dev
         cplx = codegen.DTYPES[dt][1]
         f32 = codegen.is_f32(dt)
         cw = 2 if cplx else 1
         tdt = torch.complex128 if cplx else torch.float64            # small matrix C
         sdt = (torch.complex64 if cplx else torch.float32) if f32 else tdt  # storage of A, B
-        cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
-        if args.prune:
-            # the performance model drops candidates predicted far slower than
-            # the best prediction (register use from the tuning build's records)
-            from paper_1905_03136_amd import build, model
-            res = build.variant_resources(cands, tag="_" + args.prune_tag)
-            kept = model.prune(cands, K, res, args.prune)
-            print("[tune] %s %s %dx%d: model keeps %d of %d candidates" % (op, dt, M, N, len(kept), len(cands)),
-                  flush=True)
-            cands = kept
-        if not cands:
-            continue
         # integer-valued problem: every candidate must give the exact product
         kc = 4099
         Ah = inputs.host_integers(kc, M, 7, inputs.STREAM_A, cplx)
@@ -178,15 +162,15 @@ def cmd_run(args):
         Bi = torch.from_numpy(Bh).to(dev).to(sdt)
         Xi = torch.from_numpy(Xh).to(dev)
         # buffer sets for timing (pool reinterpreted as binary32 for the precision form)
-        pool = pools[cplx].view(torch.float32) if f32 else pools[cplx]
+        pool = self.pools[cplx].view(torch.float32) if f32 else self.pools[cplx]
         ws_elems = K * (M + N) * cw
         ws_bytes = ws_elems * pool.element_size()
         R = max(1, min(int(math.ceil((1 << 30) / ws_bytes)), pool.numel() // ws_elems))
         sets = []
         for r in range(R):
-            base = pool[r * ws_elems:(r + 1) * ws_elems]
-            a = base[:K * M * cw]
-            b = base[K * M * cw:]
+            chunk = pool[r * ws_elems:(r + 1) * ws_elems]
+            a = chunk[:K * M * cw]
+            b = chunk[K * M * cw:]
             if cplx:
                 a = torch.view_as_complex(a.view(K, M, 2))
                 b = torch.view_as_complex(b.view(K, N, 2))
@@ -197,12 +181,13 @@ def cmd_run(args):
         Xs = inputs.device_uniform(M, N, 3, inputs.STREAM_C, cplx, dev)
         Cout = torch.empty((M, N), dtype=tdt, device=dev)
         byts, flops = _algorithmic(op, cplx, K, M, N, 4 if f32 else 8)
-        for v in cands:
+        out = []
+        for v in variants:
             name = codegen.variant_name(v)
-            rec = dict(op=op, dt=dt, M=M, N=N, name=name, cfg=v["cfg"], K=K)
-            if name not in names:
+            rec = dict(base or {}, op=op, dt=dt, M=M, N=N, name=name, cfg=v["cfg"], K=K)
+            if name not in self.names:
                 rec.update(ok=False, error="not compiled")
-                db.write(json.dumps(rec) + "\n")
+                out.append(rec)
                 continue
             _lib.check(_lib.tsg_force_variant(name))
             try:
@@ -219,13 +204,13 @@ def cmd_run(args):
                     ok = ok and bool(torch.equal(once(), exact))
                 finally:
                     _lib.tsg_set_grid_limit(0)
-                for w in range(args.warmup):
+                for w in range(self.warmup):
                     call(sets[w % R])
                 evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                       for _ in range(args.reps)]
-                for i in range(args.reps):
+                       for _ in range(self.reps)]
+                for i in range(self.reps):
                     evs[i][0].record()
-                    call(sets[(args.warmup + i) % R])
+                    call(sets[(self.warmup + i) % R])
                     evs[i][1].record()
                 torch.cuda.synchronize()
                 times = sorted(e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs)
@@ -236,15 +221,165 @@ def cmd_run(args):
                            roof_frac=round(roof / t, 4))
             finally:
                 _lib.tsg_force_variant(None)
+            out.append(rec)
+        return out
+
+
+def _read_db(path, key):
+    done = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                try:
+                    r = json.loads(line)
+                    done[key(r)] = r
+                except (ValueError, KeyError):
+                    pass
+    return done
+
+
+def _show(rec):
+    print("[tune] %-50s %9.1f us %7.1f GB/s roof %.3f %s" % (
+        rec["name"] + ("" if "cls" not in rec else " %dx%d" % (rec["M"], rec["N"])), rec.get("us", -1),
+        rec.get("GBps", 0), rec.get("roof_frac", 0), "" if rec["ok"] else rec.get("error", "MISMATCH")), flush=True)
+
+
+def cmd_run(args):
+    os.environ.setdefault("TSG_LIBRARY", TUNE_LIB)
+    sys.path.insert(0, ROOT)
+    from paper_1905_03136_amd import codegen
+    timer = _Timer(args.K, args.warmup, args.reps)
+    groups = {}
+    for v in codegen.tuning_variants(_widths(args.widths)):
+        if v["M"] == 0:
+            continue
+        groups.setdefault((v["op"], v["dt"], v["M"], v["N"]), []).append(v)
+    done = _read_db(args.db, lambda r: r["name"])
+    db = open(args.db, "a")
+    t_start = time.time()
+    dtypes = set(args.dtypes.split(",")) if args.dtypes else None
+    ops = set(args.ops.split(",")) if args.ops else None
+    for key in sorted(groups, key=lambda k: (k[0], k[1], k[2] * k[3])):
+        op, dt, M, N = key
+        if (dtypes and dt not in dtypes) or (ops and op not in ops):
+            continue
+        cands = [v for v in groups[key] if codegen.variant_name(v) not in done]
+        if args.prune:
+            # the performance model drops candidates predicted far slower than
+            # the best prediction (register use from the tuning build's records)
+            from paper_1905_03136_amd import build, model
+            res = build.variant_resources(cands, tag="_" + args.prune_tag)
+            kept = model.prune(cands, args.K, res, args.prune)
+            print("[tune] %s %s %dx%d: model keeps %d of %d candidates" % (op, dt, M, N, len(kept), len(cands)),
+                  flush=True)
+            cands = kept
+        for rec in timer.measure(op, dt, M, N, cands):
             db.write(json.dumps(rec) + "\n")
             db.flush()
-            done[name] = rec
-            print("[tune] %-50s %9.1f us %7.1f GB/s roof %.3f %s" % (
-                name, rec.get("us", -1), rec.get("GBps", 0), rec.get("roof_frac", 0), "" if rec["ok"] else "MISMATCH"),
-                flush=True)
+            done[rec["name"]] = rec
+            _show(rec)
     db.close()
     print("[tune] done in %.0f s" % (time.time() - t_start), flush=True)
     write_table(args.db, args.out, args.merge)
+
+
+def generic_tuning_variants():
+    """Every candidate of every run-time-width class of the autotuned types,
+    each with the widths its configuration can compute (so that a forced
+    variant never runs beyond them)."""
+    from paper_1905_03136_amd import codegen
+    out, seen = [], set()
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        for dt in codegen.GEN_TUNED_DTYPES:
+            for cls in classes:
+                for cfg in codegen.generic_candidates(op, dt, cls):
+                    mx, nx = codegen.generic_capacity(op, cfg)
+                    v = dict(op=op, dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=cfg)
+                    if codegen.variant_name(v) not in seen:
+                        seen.add(codegen.variant_name(v))
+                        out.append(v)
+    return out
+
+
+def cmd_generic(args):
+    """GPU: time the candidates of every run-time-width class on the class's
+    pairs and write the choice of each class (the fastest correct one by the
+    mean over the pairs of its time over the pair's best time) into the
+    table's "generic" list."""
+    sys.path.insert(0, ROOT)
+    from paper_1905_03136_amd import build, codegen
+    os.environ.setdefault("TSG_LIBRARY", build.tagged_lib(args.tag))
+    timer = _Timer(args.K, args.warmup, args.reps)
+    done = _read_db(args.db, lambda r: (r["name"], r["M"], r["N"]))
+    db = open(args.db, "a")
+    t_start = time.time()
+    ops = set(args.ops.split(",")) if args.ops else None
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        if ops and op not in ops:
+            continue
+        for dt in codegen.GEN_TUNED_DTYPES:
+            for cls in classes:
+                vs = []
+                for cfg in codegen.generic_candidates(op, dt, cls):
+                    mx, nx = codegen.generic_capacity(op, cfg)
+                    vs.append(dict(op=op, dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=cfg))
+                for M, N in codegen.generic_pairs(op, cls):
+                    todo = [v for v in vs if (codegen.variant_name(v), M, N) not in done]
+                    for rec in timer.measure(op, dt, M, N, todo, base=dict(cls=list(cls))):
+                        db.write(json.dumps(rec) + "\n")
+                        db.flush()
+                        done[(rec["name"], M, N)] = rec
+                        if args.verbose or not rec["ok"]:
+                            _show(rec)
+                print("[tune] %s %s class %dx%d: %d candidates timed (%.0f s)" % (
+                    op, dt, cls[0], cls[1], len(vs), time.time() - t_start), flush=True)
+    db.close()
+    write_generic(args.db, args.out)
+
+
+def write_generic(db_path, out_path):
+    """The "generic" list of the table from a database of class timings."""
+    from paper_1905_03136_amd import codegen
+    recs = {}
+    with open(db_path) as f:
+        for line in f:
+            try:
+                r = json.loads(line)
+            except ValueError:
+                continue
+            if "cls" in r:
+                recs[(r["name"], r["M"], r["N"])] = r
+    entries = []
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        for dt in codegen.GEN_TUNED_DTYPES:
+            for cls in classes:
+                pairs = codegen.generic_pairs(op, cls)
+                by = {}
+                for (name, M, N), r in recs.items():
+                    if r["op"] == op and r["dt"] == dt and tuple(r["cls"]) == tuple(cls):
+                        by.setdefault(name, {})[(M, N)] = r
+                # a candidate counts only if it is exact and timed on every pair
+                full = {n: d for n, d in by.items()
+                        if all(p in d and d[p].get("ok") and d[p].get("us") for p in pairs)}
+                if not full:
+                    continue
+                best = {p: min(d[p]["us"] for d in full.values()) for p in pairs}
+                score = {n: sum(d[p]["us"] / best[p] for p in pairs) / len(pairs) for n, d in full.items()}
+                win = min(score, key=score.get)
+                d = full[win]
+                mx, nx = codegen.generic_limits(op, cls)
+                entries.append(dict(op=op, dt=dt, maxM=mx, maxN=nx, cfg=d[pairs[0]]["cfg"], name=win,
+                                    score=round(score[win], 4), candidates=len(full),
+                                    pairs=[[M, N, d[(M, N)]["us"], d[(M, N)]["roof_frac"]] for M, N in pairs]))
+    tab = {"entries": []}
+    if os.path.exists(out_path):
+        with open(out_path) as f:
+            tab = json.load(f)
+    tab["generic"] = entries
+    with open(out_path, "w") as f:
+        json.dump(tab, f, indent=1)
+        f.write("\n")
+    print("[tune] wrote %s (%d run-time-width classes)" % (out_path, len(entries)), flush=True)
 
 
 def cmd_batched(args):
@@ -357,14 +492,16 @@ def write_table(db_path, out_path, merge=None):
             e.update(plain_cfg=plain[k]["cfg"], plain_name=plain[k]["name"], plain_us=plain[k]["us"])
         entries.append(e)
     tab = {"entries": entries}
-    # the batched form's tuned parameters are kept from the merged table
-    for src in (merge, out_path):
-        if src and os.path.exists(src):
-            with open(src) as f:
-                b = json.load(f).get("batched")
-            if b:
-                tab["batched"] = b
-                break
+    # the batched form's parameters and the run-time-width classes are kept
+    # from the merged table
+    for key in ("batched", "generic"):
+        for src in (merge, out_path):
+            if src and os.path.exists(src):
+                with open(src) as f:
+                    b = json.load(f).get(key)
+                if b:
+                    tab[key] = b
+                    break
     with open(out_path, "w") as f:
         json.dump(tab, f, indent=1)
         f.write("\n")
@@ -502,13 +639,14 @@ def main(argv=None):
     b.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
     b.add_argument("--kinds", default="", help="comma-separated subset of the mappings (valu,packed,mfma,a32,lds)")
     b.add_argument("--with-tuned", action="store_true", help="add each width's configuration in tuned.json")
-    b.add_argument("--tag", default="", help="build libtsgemm_<tag>.so apart from the default tuning library")
+    b.add_argument("--tag", default="", help="build _build/libtsgemm_<tag>.so apart from the default tuning library")
+    b.add_argument("--generic", action="store_true", help="the candidates of the run-time-width classes")
     r = sub.add_parser("run")
     r.add_argument("--widths", default="graded")
     r.add_argument("--dtypes", default="", help="comma-separated subset of r64,c128,r32,c64,r32a,c64a")
     r.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
     r.add_argument("--K", type=int, default=1 << 24)
-    r.add_argument("--db", default="gpurun_out/tune_db.jsonl")
+    r.add_argument("--db", default="tune_db.jsonl")
     r.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
     r.add_argument("--reps", type=int, default=5)
     r.add_argument("--warmup", type=int, default=2)
@@ -531,10 +669,20 @@ def main(argv=None):
     bt.add_argument("--lags", default="0,4,16,32")
     bt.add_argument("--reps", type=int, default=5)
     bt.add_argument("--warmup", type=int, default=2)
-    bt.add_argument("--db", default="gpurun_out/tune_batched.jsonl")
+    bt.add_argument("--db", default="tune_batched.jsonl")
     bt.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
+    g = sub.add_parser("generic", help="GPU: configurations of the run-time-width classes")
+    g.add_argument("--K", type=int, default=1 << 24)
+    g.add_argument("--ops", default="", help="comma-separated subset of tsmttsm,tsmm")
+    g.add_argument("--tag", default="generic", help="library built by 'build --generic --tag <tag>'")
+    g.add_argument("--db", default="tune_generic.jsonl")
+    g.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
+    g.add_argument("--reps", type=int, default=5)
+    g.add_argument("--warmup", type=int, default=2)
+    g.add_argument("--verbose", action="store_true", help="print every timing")
+    g.add_argument("--table-only", action="store_true", help="only write the table from the database")
     t = sub.add_parser("table")
-    t.add_argument("--db", default="gpurun_out/tune_db.jsonl")
+    t.add_argument("--db", default="tune_db.jsonl")
     t.add_argument("--out", default=os.path.join(HERE, "tuned.json"))
     t.add_argument("--merge", default="")
     a = ap.parse_args(argv)
@@ -548,6 +696,11 @@ def main(argv=None):
         cmd_batched(a)
     elif a.cmd == "heatmap":
         cmd_heatmap(a)
+    elif a.cmd == "generic":
+        if a.table_only:
+            write_generic(a.db, a.out)
+        else:
+            cmd_generic(a)
     else:
         write_table(a.db, a.out, a.merge)
 

@@ -86,3 +86,74 @@ def test_batched_parameters_reach_the_generated_table(tmp_path):
     files = codegen.emit(str(tmp_path / "gen"), [], batched=b)
     text = open([f for f in files if f.endswith("tsg_table.hip")][0]).read()
     assert "const int64_t kOrthItemBytes = 8388608;" in text and "const int kOrthLag = 16;" in text
+
+
+def _first_cover(gens, M, N):
+    for g in gens:
+        if M <= g["maxM"] and N <= g["maxN"]:
+            return g
+    return None
+
+
+def test_runtime_width_classes_listed_before_their_containers():
+    """A class precedes every class that contains it, so the first record
+    covering (M, N) is the tightest class."""
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        for i, a in enumerate(classes):
+            for b in classes[:i]:
+                assert not (a[0] <= b[0] and a[1] <= b[1]), (op, a, b)
+
+
+def test_runtime_width_pairs_lie_in_their_class():
+    """The pairs a class is tuned on are non-square and run on that class."""
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        for cls in classes:
+            lims = [codegen.generic_limits(op, c) for c in classes]
+            for M, N in codegen.generic_pairs(op, cls):
+                assert M != N
+                first = next(i for i, (mx, nx) in enumerate(lims) if M <= mx and N <= nx)
+                assert classes[first] == cls, (op, cls, M, N)
+
+
+def test_runtime_width_candidates_compute_their_class(tmp_path):
+    """Every candidate of a class, and whatever the table picks, computes at
+    least the widths the class serves (a forced or chosen kernel never runs
+    beyond its blocks); a synthetic table's choices are the ones emitted."""
+    import json
+    entries = []
+    for op, classes in (("tsmttsm", codegen.GEN_TSMTTSM_CLASSES), ("tsmm", codegen.GEN_TSMM_CLASSES)):
+        for dt in codegen.GEN_TUNED_DTYPES:
+            for cls in classes:
+                mx, nx = codegen.generic_limits(op, cls)
+                cands = codegen.generic_candidates(op, dt, cls)
+                assert cands, (op, dt, cls)
+                for c in cands:
+                    cm, cn = codegen.generic_capacity(op, c)
+                    assert cm >= mx and cn >= nx, (op, dt, cls, c)
+                entries.append(dict(op=op, dt=dt, maxM=mx, maxN=nx, cfg=cands[-1]))
+    path = tmp_path / "tuned.json"
+    path.write_text(json.dumps({"entries": [], "generic": entries}))
+    gens = codegen.generic_variants(str(path))
+    for op in codegen.OPS:
+        for dt in codegen.GEN_TUNED_DTYPES:
+            mine = [g for g in gens if g["op"] == op and g["dt"] == dt and not g["cfg"].get("RB")]
+            for M, N in itertools.product(range(1, 65), repeat=2):
+                g = _first_cover(mine, M, N)
+                assert g is not None, (op, dt, M, N)
+                if g["cfg"]["kind"] == "mfma":
+                    cm, cn = codegen.generic_capacity(op, g["cfg"])
+                    assert M <= cm and N <= cn
+            for cls in (codegen.GEN_TSMTTSM_CLASSES if op == "tsmttsm" else codegen.GEN_TSMM_CLASSES):
+                mx, nx = codegen.generic_limits(op, cls)
+                want = [e["cfg"] for e in entries if (e["op"], e["dt"], e["maxM"], e["maxN"]) == (op, dt, mx, nx)]
+                got = [g["cfg"] for g in mine if (g["maxM"], g["maxN"]) == (mx, nx)]
+                assert got == want, (op, dt, cls)
+
+
+def test_product_runtime_width_variants_fit_their_kernels():
+    """In the shipped table every run-time-width record's widths lie within
+    what its kernel computes (and the beta != 0 twins within theirs)."""
+    for g in codegen.generic_variants():
+        if g["cfg"]["kind"] == "mfma":
+            cm, cn = codegen.generic_capacity(g["op"], g["cfg"])
+            assert g["maxM"] <= cm and g["maxN"] <= cn, codegen.variant_name(g)
