@@ -252,6 +252,23 @@ def _mfma_slices(ms, nb, cplx, va=False, nbufs=(2, 3, 4)):
     return out
 
 
+def _slab_slices(ms, nb, M, es, fl):
+    """TSMM configurations with slab reads of A (runs of 16 U rows of M
+    elements of es bytes, loads of fl elements per lane), for a contraction
+    depth of ms slices and nb column blocks; M is the widest run (for
+    run-time widths: 4 ms)."""
+    out = []
+    for u in (1, 2, 4):
+        for w in (4, 8):
+            for nbuf in (2, 3):
+                nl = _ceil(16 * u * M, 64 * fl) * fl * es // 8   # registers (doubles) per lane and tile
+                ops = nbuf * nl + u * ms + u * nb * 4
+                lds = w * 16 * u * M * es + ms * nb * 64 * 8
+                if ops <= (96 if w == 8 else 160) and lds <= 64 * 1024 and (nbuf == 2 or u <= 2):
+                    out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, FL=fl))
+    return out
+
+
 def _candidates(op, dt, M, N):
     cw = 2 if DTYPES[dt][1] else 1
     cplx = DTYPES[dt][1]
@@ -341,14 +358,7 @@ def _candidates(op, dt, M, N):
         if not cplx:
             es = 4 if is_f32(dt) else 8                       # bytes per stored element
             fl = max(f for f in (1, 2, 4) if M % f == 0 and f * es <= 16)
-            for u in (1, 2, 4):
-                for w in (4, 8):
-                    for nbuf in (2, 3):
-                        nl = _ceil(16 * u * M, 64 * fl) * fl * es // 8   # registers (doubles) per lane and tile
-                        ops = nbuf * nl + u * ms + u * nb * 4
-                        lds = w * 16 * u * M * es + ms * nb * 64 * 8
-                        if ops <= (96 if w == 8 else 160) and lds <= 64 * 1024 and (nbuf == 2 or u <= 2):
-                            out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, FL=fl))
+            out += _slab_slices(ms, nb, M, es, fl)
     return out
 
 
@@ -471,7 +481,11 @@ def generic_candidates(op, dt, cls):
         ms, nb = cls
         shapes = [(ms, nb), (_next(GEN_TSMM_MS, ms), nb), (ms, _next((1, 2, 3, 4), nb))]
         for sh in shapes:
-            for c in _mfma_slices(sh[0], sh[1], cplx, nbufs=(2, 3)):
+            cs = _mfma_slices(sh[0], sh[1], cplx, nbufs=(2, 3))
+            if not cplx and not is_f32(dt):
+                # slab reads of A with single-element loads (any M; rows contiguous)
+                cs += _slab_slices(sh[0], sh[1], 4 * sh[0], 8, 1)
+            for c in cs:
                 key = json.dumps(c, sort_keys=True)
                 if key not in seen:
                     seen.add(key)
@@ -505,7 +519,10 @@ def tuned_generic(path=None):
     if os.path.exists(path):
         with open(path) as f:
             for e in json.load(f).get("generic", []):
-                out[(e["op"], e["dt"], int(e["maxM"]), int(e["maxN"]))] = e["cfg"]
+                key = (e["op"], e["dt"], int(e["maxM"]), int(e["maxN"]))
+                out[key] = e["cfg"]
+                if e.get("plain_cfg"):
+                    out[key + ("plain",)] = e["plain_cfg"]
     return out
 
 
@@ -563,16 +580,27 @@ def generic_variants(tuned_path=None):
                 cfg = tuned.get(("tsmm", dt, mx, nx))
                 if cfg:
                     tsmm.append((mx, nx, cfg))
+                    # slab reads need contiguous rows: the fastest kernel
+                    # without that need follows for other layouts
+                    if needs_layout(cfg):
+                        plain = tuned.get(("tsmm", dt, mx, nx, "plain"))
+                        if not plain:
+                            u, w = _gen_tsmm_cfg(cfg["MS"], cfg["NB"], cplx)
+                            plain = dict(kind="mfma", MS=cfg["MS"], NB=cfg["NB"], U=u, WPB=w)
+                        tsmm.append((mx, nx, plain))
         else:
             tsmm = []
             shapes = [(1, 1), (2, 1)] + [(ms, nb) for ms in (4, 6, 8, 12, 16) for nb in (1, 2, 4)]
             for ms, nb in shapes:
                 u, w = _gen_tsmm_cfg(ms, nb, cplx)
                 tsmm.append((4 * ms, 16 * nb, dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w)))
+        done = set()
         for mx, nx, cfg in tsmm:
             # a twin reading the old B with A serves calls with beta != 0 (its
             # register ring of B does not fit eight-wave blocks from 6 slices)
-            out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=_tsmm_rb(cfg, cplx)))
+            if (mx, nx) not in done:
+                done.add((mx, nx))
+                out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=_tsmm_rb(cfg, cplx)))
             out.append(dict(op="tsmm", dt=dt, M=0, N=0, maxM=mx, maxN=nx, cfg=cfg))
     return out
 

@@ -156,6 +156,33 @@ __device__ __forceinline__ void slab_put(SR* lds, int lane, const SV (&v)[NL])
     __asm__ volatile("" ::: "memory");
 }
 
+// Run-time run length n (single-element loads, n at most 64 NL): load i of
+// the lane is issued only where its element lies in the run; elements past
+// the end of the matrix are clamped to its last one (their values are never
+// used), and slab_put_n writes only the run's n elements.
+template <int NL, class SR>
+__device__ __forceinline__ void slab_load_n(const SR* p, int64_t e0, int64_t total, int lane, int n, SR (&v)[NL])
+{
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int o = i * kWave + lane;
+        if (o < n) {
+            const int64_t e = e0 + o;
+            v[i] = __builtin_nontemporal_load(p + (e < total ? e : total - 1));
+        }
+    }
+}
+template <int NL, class SR>
+__device__ __forceinline__ void slab_put_n(SR* lds, int lane, int n, const SR (&v)[NL])
+{
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int o = i * kWave + lane;
+        if (o < n) lds[o] = v[i];
+    }
+    __asm__ volatile("" ::: "memory");
+}
+
 // Element (m, n) of TSMM's small operand op(C): opc 0 reads C(m, n) = C[m ldc + n];
 // opc 1 (transpose) and 2 (conjugate transpose, the caller negates the
 // imaginary part) read C[n ldc + m] of a stored N x M matrix.
@@ -1129,13 +1156,17 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     // order, so no barrier is needed.
     static_assert(!VA || (!CPLX && !F32 && MS % 2 == 0), "paired A loads: binary64 real data, M a multiple of 8");
     static_assert(CPLX || !G3, "the three-product form is for complex data");
-    static_assert(FL == 0 || (!CPLX && !VA && MC > 0 && MC % FL == 0), "slab reads: real data, M a multiple of FL");
+    static_assert(FL == 0 || (!CPLX && !VA && (MC > 0 ? MC % FL == 0 : FL == 1)),
+                  "slab reads: real data, M a multiple of FL (run-time widths: single-element loads)");
     using T = elem_t<CPLX>;
     using S = typename storage<CPLX, F32>::type;  // storage type of A and B
     constexpr int CW = CPLX ? 2 : 1;
     constexpr int RT = 16 * U * WPB;
     constexpr int NFRAG = MS * NB * kWave;
-    constexpr int SLAB = FL ? 16 * U * MC : 0;               // elements of A per wave and tile
+    // slab reads with a run-time M (FL = 1): the region holds the widest run
+    // the slices cover, 16 U rows of 4 MS elements; a tile's run is 16 U M
+    constexpr int MCAP = MC ? MC : 4 * MS;
+    constexpr int SLAB = FL ? 16 * U * MCAP : 0;             // elements of A per wave and tile
     constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
     using SR = typename real_of<S>::type;                         // real storage type (slab reads)
     using SV = typename slab_vec<SR, FL ? FL : 1>::type;          // one slab load of a lane
@@ -1210,12 +1241,18 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                         f.ob[u][j][r] = ld_stream(B + rc * ldb + nc);
                     }
         }
-        if constexpr (FL) {
+        if constexpr (FL && MC > 0) {
             // the wave's run starts at row t RT + 16 U wave; positions past
             // the end of A are clamped to its last FL elements (K M is a
             // multiple of FL), their rows are never stored
             const int64_t base = (t * RT + (int64_t)wave * U * 16) * MC;
             slab_load<FL, NL>(reinterpret_cast<const SR*>(A), base, KM, lane, f.v);
+            return;
+        } else if constexpr (FL) {
+            // run-time M: only the loads inside the run of 16 U M elements
+            // are issued (single elements, clamped to the last element of A)
+            const int64_t base = (t * RT + (int64_t)wave * U * 16) * M;
+            slab_load_n<NL>(reinterpret_cast<const SR*>(A), base, KM, lane, 16 * U * M, f.v);
             return;
         } else {
 #pragma unroll
@@ -1243,12 +1280,15 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         __asm__ volatile("" ::: "memory");
         T av[U][MS];  // matrix-core A operands of the tile
         if constexpr (FL) {
-            slab_put<FL, NL, SLAB>(mine, lane, f.v);
+            if constexpr (MC > 0)
+                slab_put<FL, NL, SLAB>(mine, lane, f.v);
+            else
+                slab_put_n<NL>(mine, lane, 16 * U * M, f.v);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int s = 0; s < MS; ++s)
-                    av[u][s] = keep(kok[s], (double)mine[(u * 16 + lc) * MC + koff[s]]);
+                    av[u][s] = keep(kok[s], (double)mine[(u * 16 + lc) * M + koff[s]]);
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u)

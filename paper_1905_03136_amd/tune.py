@@ -368,9 +368,17 @@ def write_generic(db_path, out_path):
                 win = min(score, key=score.get)
                 d = full[win]
                 mx, nx = codegen.generic_limits(op, cls)
-                entries.append(dict(op=op, dt=dt, maxM=mx, maxN=nx, cfg=d[pairs[0]]["cfg"], name=win,
-                                    score=round(score[win], 4), candidates=len(full),
-                                    pairs=[[M, N, d[(M, N)]["us"], d[(M, N)]["roof_frac"]] for M, N in pairs]))
+                e = dict(op=op, dt=dt, maxM=mx, maxN=nx, cfg=d[pairs[0]]["cfg"], name=win,
+                         score=round(score[win], 4), candidates=len(full),
+                         pairs=[[M, N, d[(M, N)]["us"], d[(M, N)]["roof_frac"]] for M, N in pairs])
+                # the fastest configuration without layout requirements on A
+                # (served to calls whose rows are not contiguous)
+                if codegen.needs_layout(e["cfg"]):
+                    plain = {n: sc for n, sc in score.items() if not codegen.needs_layout(full[n][pairs[0]]["cfg"])}
+                    if plain:
+                        pw = min(plain, key=plain.get)
+                        e.update(plain_cfg=full[pw][pairs[0]]["cfg"], plain_name=pw, plain_score=round(plain[pw], 4))
+                entries.append(e)
     tab = {"entries": []}
     if os.path.exists(out_path):
         with open(out_path) as f:

@@ -103,3 +103,29 @@ def test_narrow_pairs_use_shallow_matrix_core_variants(M, N, cplx):
     X = inputs.host_integers(M, N, 63, inputs.STREAM_C, cplx)
     got = api.tsmm(torch.from_numpy(A).to(DEV), torch.from_numpy(X).to(DEV)).cpu().numpy()
     assert np.array_equal(got, oracle.tsmm(A, X))
+
+
+@pytest.mark.parametrize("M,N", [(33, 40), (21, 9), (57, 50), (13, 60)])
+def test_strided_rows_use_a_variant_without_slab_reads(M, N):
+    """Run-time-width TSMM classes whose fastest kernel reads A in slabs
+    (contiguous rows) keep a kernel without that need for a leading dimension
+    above M; both give the oracle's result bit for bit."""
+    A = inputs.host_integers(K, M, 64, inputs.STREAM_A, False)
+    X = inputs.host_integers(M, N, 64, inputs.STREAM_C, False)
+    ref = oracle.tsmm(A, X)
+    wide = np.zeros((K, M + 3))
+    wide[:, :M] = A
+    dW = torch.from_numpy(wide).to(DEV)
+    dA = dW[:, :M]
+    assert dA.stride(0) == M + 3
+    flat = torch.from_numpy(A).to(DEV)
+    dX = torch.from_numpy(X).to(DEV)
+    print("strided M=%d N=%d" % (M, N), flush=True)
+    for a in (flat, dA):
+        for grid in (0, 3):
+            assert _lib.tsg_set_grid_limit(grid) == 0
+            try:
+                got = api.tsmm(a, dX).cpu().numpy()
+            finally:
+                _lib.tsg_set_grid_limit(0)
+            assert np.array_equal(got, ref), (a.stride(0), grid)
