@@ -232,10 +232,12 @@ def _mfma_blocks(mbt, nb, cplx, nbufs=(2, 3, 4), occ=True):
     return out
 
 
-def _mfma_slices(ms, nb, cplx, va=False, nbufs=(2, 3, 4)):
+def _mfma_slices(ms, nb, cplx, va=False, nbufs=(2, 3, 4), cg=False):
     """Matrix-core TSMM configurations for a contraction depth of ms 4-wide
     slices and nb 16-column blocks of B (shared by the exact-width and
-    run-time-width variants); ``va`` adds the paired loads of A."""
+    run-time-width variants); ``va`` adds the paired loads of A, ``cg`` a
+    twin of each plain one that reads its C operands from global memory at
+    every tile instead of the LDS copy (an ablation of the C source)."""
     cw = 2 if cplx else 1
     out = []
     for u in (1, 2, 4):
@@ -246,6 +248,8 @@ def _mfma_slices(ms, nb, cplx, va=False, nbufs=(2, 3, 4)):
                     if va:
                         out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, VA=1))
                     out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
+                    if cg:
+                        out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, CG=1))
                     # complex three-product form: one more accumulator set, C staged three times
                     if cplx and ops + u * nb * 4 <= (96 if w == 8 else 160):
                         out.append(dict(kind="mfma", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
@@ -352,7 +356,7 @@ def _candidates(op, dt, M, N):
     # vector and packed kernels stay ahead)
     if M >= 3 or N >= 16:
         ms, nb = _ceil(M, 4), _ceil(N, 16)
-        out += _mfma_slices(ms, nb, cplx, va=not cplx and M % 8 == 0)
+        out += _mfma_slices(ms, nb, cplx, va=not cplx and M % 8 == 0, cg=True)
         # slab reads of A (rows contiguous): the wave's 16 U rows as one run of
         # loads of up to 16 bytes per lane, redistributed through LDS
         if not cplx:
@@ -710,6 +714,8 @@ def variant_name(v):
         tag += "_t"
     if c.get("RB"):
         tag += "_rb"
+    if c.get("CG"):
+        tag += "_cg"
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -743,10 +749,10 @@ def _template(v):
         return "tsg::tsmm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (
             M, N, c["MX"], c["NX"], c["U"], cplx, "true" if c["VA"] else "false",
             "true" if c["VB"] else "false", c["WPB"])
-    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s, %d, %s>" % (
+    return "tsg::tsmm_mfma<%d, %d, %d, %d, %d, %s, %d, %d, %s, %d, %s, %s, %d, %s, %s>" % (
         M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, "true" if c.get("VA") else "false",
         c.get("OCC", 1), f32, "true" if c.get("G3") else "false", c.get("FL", 0),
-        "true" if c.get("RB") else "false")
+        "true" if c.get("RB") else "false", "true" if c.get("CG") else "false")
 
 
 def rows_per_tile(v):

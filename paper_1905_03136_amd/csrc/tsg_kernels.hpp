@@ -1132,7 +1132,7 @@ tsmm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 // lanes write 128 consecutive bytes of a row.
 // ============================================================================
 template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, bool VA = false, int OCC = 1,
-          bool F32 = false, bool G3 = false, int FL = 0, bool RB = false>
+          bool F32 = false, bool G3 = false, int FL = 0, bool RB = false, bool CG = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
           const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
@@ -1170,7 +1170,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
     using SR = typename real_of<S>::type;                         // real storage type (slab reads)
     using SV = typename slab_vec<SR, FL ? FL : 1>::type;          // one slab load of a lane
-    __shared__ double cf[NFRAG * (G3 ? 3 : CW)];
+    __shared__ double cf[CG ? 1 : NFRAG * (G3 ? 3 : CW)];
     __shared__ __attribute__((aligned(16))) SR slab[FL ? WPB * SLAB : 1];
 
     const S* __restrict__ A = static_cast<const S*>(Av);
@@ -1184,7 +1184,9 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     const bool read_b = beta != 0.0;
 
     // Stage C in fragment order: cf[(s * NB + j) * 64 + l] = C(m(s, l/16), 16j + l%16).
-    for (int idx = threadIdx.x; idx < NFRAG; idx += blockDim.x) {
+    // CG (an ablation of the C source): no copy; every tile reads the lane's C
+    // operands from global memory through the caches instead.
+    for (int idx = threadIdx.x; idx < (CG ? 0 : NFRAG); idx += blockDim.x) {
         const int l = idx & (kWave - 1);
         const int sj = idx / kWave;
         const int s = sj / NB, j = sj - (sj / NB) * NB;
@@ -1203,6 +1205,26 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         }
     }
     __syncthreads();
+
+    // C operand `part` (0: real part, 1: imaginary, 2: their sum) of slice s
+    // and column block j for this lane
+    auto cfrag = [&](int part, int s, int j) -> double {
+        if constexpr (!CG) {
+            return cf[part * NFRAG + (s * NB + j) * kWave + lane];
+        } else {
+            const int m = VA ? 8 * (s >> 1) + 2 * lr + (s & 1) : 4 * s + lr;
+            const int n = 16 * j + lc;
+            if (m >= M || n >= N) return 0.0;
+            const int64_t ci = small_index(m, n, ldc, opc);
+            if constexpr (!CPLX) {
+                return Cm[ci];
+            } else {
+                const double re = Cm[2 * ci];
+                const double im = opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1];
+                return part == 0 ? re : (part == 1 ? im : re + im);
+            }
+        }
+    };
 
     int koff[MS];
     bool kok[MS];
@@ -1311,7 +1333,7 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             if constexpr (!CPLX) {
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const double cr = cf[(s * NB + j) * kWave + lane];
+                    const double cr = cfrag(0, s, j);
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u][j] = mfma16(av[u][s], cr, acc[u][j]);
                 }
@@ -1324,19 +1346,19 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const double cr = cf[(s * NB + j) * kWave + lane];
+                    const double cr = cfrag(0, s, j);
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u][j] = mfma16(av[u][s].re, cr, acc[u][j]);
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const double ci = cf[NFRAG + (s * NB + j) * kWave + lane];
+                    const double ci = cfrag(1, s, j);
 #pragma unroll
                     for (int u = 0; u < U; ++u) acci[u][j] = mfma16(ai[u], ci, acci[u][j]);
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const double cs = cf[2 * NFRAG + (s * NB + j) * kWave + lane];
+                    const double cs = cfrag(2, s, j);
 #pragma unroll
                     for (int u = 0; u < U; ++u) accs[u][j] = mfma16(sa[u], cs, accs[u][j]);
                 }
@@ -1346,8 +1368,8 @@ tsmm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 double cr[NB], ci[NB];
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    cr[j] = cf[(s * NB + j) * kWave + lane];
-                    ci[j] = cf[NFRAG + (s * NB + j) * kWave + lane];
+                    cr[j] = cfrag(0, s, j);
+                    ci[j] = cfrag(1, s, j);
                 }
 #pragma unroll
                 for (int j = 0; j < NB; ++j)

@@ -138,11 +138,48 @@ def latency(sizes=(1 << 20, 64 << 20, 4 * GiB), steps=20000, stride_bytes=256):
     return out
 
 
+def markdown(res):
+    """Tables of a probe run's JSON (no GPU needed)."""
+    out = []
+    t1 = res["table1"]
+    occs = sorted({int(k.split(",")[0]) for k in t1})
+    ilps = sorted({int(k.split(",")[1]) for k in t1})
+    out.append("**Read bandwidth (GB/s) against blocks of 256 threads per CU (rows) and 16-byte loads in flight "
+               "per thread (columns)** -- the paper's Table 1 grid\n")
+    out.append("| blocks/CU \\\\ loads | " + " | ".join(str(i) for i in ilps) + " |")
+    out.append("|---|" + "---:|" * len(ilps))
+    for o in occs:
+        out.append("| %d | " % o + " | ".join("%.0f" % t1["%d,%d" % (o, i)] for i in ilps) + " |")
+    out.append("\n**Read:write mixes** (bytes read : bytes written; best launch shape of the probe)\n")
+    out.append("| mix | GB/s (read + write) | blocks/CU | loads in flight |")
+    out.append("|---|---:|---:|---:|")
+    for k, v in res["mixes"].items():
+        out.append("| %s | %.0f | %d | %d |" % (k, v["GBps"], v["blocks_per_cu"], v["loads_in_flight"]))
+    out.append("\n**Peak arithmetic (TFLOP/s) against blocks of 256 threads per CU**\n")
+    pk = res["peaks"]
+    cols = sorted({int(b) for v in pk.values() for b in v})
+    out.append("| unit | " + " | ".join(str(c) for c in cols) + " |")
+    out.append("|---|" + "---:|" * len(cols))
+    for k, v in pk.items():
+        out.append("| %s | " % k + " | ".join("%.1f" % v[str(c)] if str(c) in v else "" for c in cols) + " |")
+    out.append("\n**Load latency by pointer chasing** (one lane, dependent loads over a working set)\n")
+    out.append("| working set | cycles | ns |")
+    out.append("|---:|---:|---:|")
+    for k, v in sorted(res["latency"].items(), key=lambda kv: int(kv[0])):
+        out.append("| %.0f MiB | %.0f | %.0f |" % (int(k) / 2 ** 20, v["cycles"], v["ns"]))
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="probes.json")
     ap.add_argument("--gib", type=int, default=4, help="GiB streamed by the bandwidth probes")
+    ap.add_argument("--markdown", default="", help="no GPU: print the tables of a probe run's JSON file and exit")
     a = ap.parse_args(argv)
+    if a.markdown:
+        with open(a.markdown) as f:
+            print(markdown(json.load(f)), end="")
+        return
     import torch
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

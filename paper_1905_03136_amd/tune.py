@@ -525,6 +525,7 @@ _DIMENSIONS = {
     "slab reads FL": lambda c: c.get("FL", 0),
     "vector tails TL": lambda c: c.get("TL", 0),
     "three-product form G3": lambda c: c.get("G3", 0),
+    "C source (LDS 0 / global 1) CG": lambda c: c.get("CG", 0),
 }
 
 
