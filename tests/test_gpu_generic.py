@@ -39,11 +39,35 @@ def widen(x):
     return x.astype(np.complex128 if np.iscomplexobj(x) else np.float64)
 
 
+def spilled_pairs_fall_through(name, op, dt, a, b, rb):
+    cplx = dt in ("c128", "c64")
+    tdt = {"r64": torch.float64, "c128": torch.complex128, "r32": torch.float32, "c64": torch.complex64}[dt]
+    for M, N in pairs_of(a, b):
+        print("%s (not registered) M=%d N=%d" % (name, M, N), flush=True)
+        assert api.kernel_name(op, tdt, M, N) != name
+        A = inputs.host_integers(K, M, 61, inputs.STREAM_A, cplx)
+        dA = dev(A, dt)
+        if op == "tsmttsm":
+            B = inputs.host_integers(K, N, 61, inputs.STREAM_B, cplx)
+            got = widen(api.tsmttsm(dA, dev(B, dt)).cpu().numpy())
+            assert np.array_equal(got, oracle.tsmttsm(A, B)), (M, N)
+        else:
+            X = inputs.host_integers(M, N, 61, inputs.STREAM_C, cplx)
+            B0 = inputs.host_integers(K, N, 62, inputs.STREAM_B, cplx)
+            beta = 1.0 if rb else 0.0
+            got = widen(api.tsmm(dA, torch.from_numpy(X).to(DEV), out=dev(B0, dt), beta=beta).cpu().numpy())
+            assert np.array_equal(got, oracle.tsmm(A, X, B0.copy(), alpha=1.0, beta=beta)), (M, N)
+
+
 @pytest.mark.parametrize("name,op,dt,a,b,rb", GENERIC, ids=[g[0] for g in GENERIC])
 def test_generic_variant_matches_oracle(name, op, dt, a, b, rb):
     names = {_lib.tsg_variant_name(i) for i in range(_lib.tsg_variant_count())}
     if name not in names:
-        pytest.skip("left out of the registry (spills registers)")
+        # a kernel that spills registers is left out of the registry: the
+        # runtime falls through to the next variant covering the pair, which
+        # must give the exact result
+        spilled_pairs_fall_through(name, op, dt, a, b, rb)
+        return
     cplx = dt in ("c128", "c64")
     bad = []
     try:
