@@ -122,25 +122,34 @@ def _lds_candidates(op, dt, M, N):
                 if acc > 64:
                     continue
                 for rt in (16, 32, 64):
-                    ops = (rt // 4) * (mb + nb) * cw
                     stage = 2 * (_ceil(rt * M * cw, 128) + _ceil(rt * N * cw, 128)) * 128 * 8
                     lds = max(stage, M * N * cw * 8)
                     if lds > LDS_BYTES:
                         continue
-                    for occ in (1, 2, 3, 4):
-                        waves = occ * wpb
-                        # the waves of a CU spread evenly over its four SIMDs, at most
-                        # three per SIMD, and the register model fits that many
-                        if waves % 4 or waves > 12 or occ * lds > LDS_BYTES:
+                    # IL: operand reads of a stage all at once (0) or IL steps
+                    # ahead of the products (then only IL + 1 steps of
+                    # operands are live)
+                    for il in (0, 1, 2):
+                        steps = rt // 4 if il == 0 else min(il + 1, rt // 4)
+                        if il and il + 1 > rt // 4:
                             continue
-                        if acc + ops > (104 if waves <= 8 else 80):
-                            continue
-                        c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wpb)
-                        if occ > 1:
-                            c["OCC"] = occ
-                        if g3:
-                            c["G3"] = 1
-                        out.append(c)
+                        ops = steps * (mb + nb) * cw
+                        for occ in (1, 2, 3, 4):
+                            waves = occ * wpb
+                            # the waves of a CU spread evenly over its four SIMDs, at most
+                            # three per SIMD, and the register model fits that many
+                            if waves % 4 or waves > 12 or occ * lds > LDS_BYTES:
+                                continue
+                            if acc + ops > (104 if waves <= 8 else 80):
+                                continue
+                            c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wpb)
+                            if occ > 1:
+                                c["OCC"] = occ
+                            if g3:
+                                c["G3"] = 1
+                            if il:
+                                c["IL"] = il
+                            out.append(c)
     return out
 
 
@@ -716,6 +725,8 @@ def variant_name(v):
         tag += "_rb"
     if c.get("CG"):
         tag += "_cg"
+    if c.get("IL"):
+        tag += "_il%d" % c["IL"]
     return "%s_%s_%s_%s" % (v["op"], v["dt"], w, tag)
 
 
@@ -734,9 +745,9 @@ def _template(v):
         return "tsg::tsmm_a32<%d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
             M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, c.get("FL", 0), "true" if c.get("RB") else "false")
     if c["kind"] == "lds":
-        return "tsg::tsmttsm_lds<%d, %d, %d, %d, %d, %d, %d, %s, %s, %d>" % (
+        return "tsg::tsmttsm_lds<%d, %d, %d, %d, %d, %d, %d, %s, %s, %d, %d>" % (
             M, N, c["MB"], c["NB"], c["WM"], c["WN"], c["RT"], cplx, "true" if c.get("G3") else "false",
-            c.get("OCC", 1))
+            c.get("OCC", 1), c.get("IL", 0))
     if v["op"] == "tsmttsm":
         if c["kind"] == "valu":
             return "tsg::tsmttsm_valu<%d, %d, %d, %d, %d, %s, %s, %s, %d>" % (

@@ -570,7 +570,8 @@ __device__ __forceinline__ void dma16(const double* src, double* dst)
     __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
 }
 
-template <int MC, int NC, int MB, int NB, int WM, int WN, int RT, bool CPLX, bool G3 = false, int OCC = 1>
+template <int MC, int NC, int MB, int NB, int WM, int WN, int RT, bool CPLX, bool G3 = false, int OCC = 1,
+          int IL = 0>
 __global__ void __launch_bounds__(WM * WN * kWave, OCC)
 tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
@@ -655,18 +656,28 @@ tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         const double* sa = lds + b * SS;
         const double* sb = sa + SA;
         T av[KS][MB], bv[KS][NB];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
+        auto operands = [&](int s) {
             const bool ok = t * RT + 4 * s + lr < K;
             const int r = 4 * s + lr;
 #pragma unroll
             for (int i = 0; i < MB; ++i) av[s][i] = keep(ok, lds_elem(sa, r * MC + moff[i], T{}));
 #pragma unroll
             for (int j = 0; j < NB; ++j) bv[s][j] = keep(ok, lds_elem(sb, r * NC + noff[j], T{}));
-        }
+        };
+        // IL = 0: every operand of the stage is read right after the barrier
+        // (all waves of the block then read LDS at once); IL > 0: the reads
+        // of step s + IL are issued between the products of step s, so the
+        // block's LDS reads spread over the whole stage (scheduling barriers
+        // keep the compiler from hoisting them back to the top)
+#pragma unroll
+        for (int s = 0; s < (IL ? (IL < KS ? IL : KS) : KS); ++s) operands(s);
         if (t + G < ntiles) stage(t + G, b ^ 1);
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+            if constexpr (IL > 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (s + IL < KS) operands(s + IL);
+            }
             if constexpr (!CPLX) {
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
