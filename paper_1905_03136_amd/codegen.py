@@ -153,6 +153,59 @@ def _lds_candidates(op, dt, M, N):
     return out
 
 
+def _lds32_candidates(op, dt, M, N):
+    """Binary32-arithmetic TSMTTSM with the rows staged in LDS
+    (tsmttsm_lds_a32): as _lds_candidates, stages of 16 or 32 rows (one
+    binary32 stretch is 32 rows), rows of whole 16-byte loads.  Register
+    model in binary64 units per lane: binary64 sums, binary32 stretch sums
+    and live operands (binary32: half a unit each)."""
+    out = []
+    if op != "tsmttsm" or (M <= 16 and N <= 16):
+        return out
+    cplx = DTYPES[dt][1]
+    cw = 2 if cplx else 1
+    if (M * cw) % 4 or (N * cw) % 4:
+        return out
+    mbt, nbt = _ceil(M, 16), _ceil(N, 16)
+    for wm in range(1, 9):
+        for wn in range(1, 9):
+            wpb = wm * wn
+            if wpb < 2 or wpb > 8 or wm > mbt or wn > nbt:
+                continue
+            mb, nb = _ceil(mbt, wm), _ceil(nbt, wn)
+            if (wm - 1) * mb >= mbt or (wn - 1) * nb >= nbt:
+                continue
+            for g3 in ((0, 1) if cplx else (0,)):
+                acc = mb * nb * 4 * cw + mb * nb * 4 * (3 if g3 else cw) / 2
+                if acc > 80:
+                    continue
+                for rt in (16, 32):
+                    stage = 2 * (_ceil(rt * M * cw, 256) + _ceil(rt * N * cw, 256)) * 256 * 4
+                    lds = max(stage, M * N * cw * 8)
+                    if lds > LDS_BYTES:
+                        continue
+                    for il in (0, 1, 2):
+                        if il and il + 1 > rt // 4:
+                            continue
+                        steps = rt // 4 if il == 0 else il + 1
+                        ops = steps * (mb + nb) * cw / 2
+                        for occ in (1, 2, 3, 4):
+                            waves = occ * wpb
+                            if waves % 4 or waves > 12 or occ * lds > LDS_BYTES:
+                                continue
+                            if acc + ops > (104 if waves <= 8 else 80):
+                                continue
+                            c = dict(kind="lds", MB=mb, NB=nb, WM=wm, WN=wn, RT=rt, WPB=wpb)
+                            if occ > 1:
+                                c["OCC"] = occ
+                            if g3:
+                                c["G3"] = 1
+                            if il:
+                                c["IL"] = il
+                            out.append(c)
+    return out
+
+
 def _a32_candidates(op, dt, M, N):
     """Binary32-product kernels: the blocked matrix-core mappings with binary32
     operands.  Register model in binary64 units per lane: binary64 stretch
@@ -184,7 +237,14 @@ def _a32_candidates(op, dt, M, N):
                         out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf))
                         if mw == 1 and u <= 2:
                             out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf, FL=fl))
-        return out
+                        # complex: three binary32 product sums per block (half a
+                        # unit more than the two they replace)
+                        if cplx and acc + mb * nb * 2 + ops <= (200 if w == 4 else 110):
+                            out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf, G3=1))
+                            if mw == 1 and u <= 2:
+                                out.append(dict(kind="a32", MB=mb, NB=nb, MW=mw, U=u, WPB=w, NBUF=nbuf, FL=fl,
+                                                G3=1))
+        return out + _lds32_candidates(op, dt, M, N)
     if M < 3 and N < 16:
         return out
     ms, nb = _ceil(M, 4), _ceil(N, 16)
@@ -198,6 +258,8 @@ def _a32_candidates(op, dt, M, N):
                 out.append(dict(kind="a32", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf))
                 if not cplx:
                     out.append(dict(kind="a32", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, FL=fl))
+                elif ops + u * nb * 2 <= (48 if w == 8 else 80):
+                    out.append(dict(kind="a32", MS=ms, NB=nb, U=u, WPB=w, NBUF=nbuf, G3=1))
     return out
 
 
@@ -739,13 +801,16 @@ def _template(v):
     if c["kind"] == "packed":
         return "tsg::%s_packed<%d, %d, %d, %s, %d, %d, %s>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf, f32)
     if c["kind"] == "a32" and v["op"] == "tsmttsm":
-        return "tsg::tsmttsm_a32<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %d>" % (
-            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), c.get("FL", 0))
+        return "tsg::tsmttsm_a32<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %d, %s>" % (
+            M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), c.get("FL", 0),
+            "true" if c.get("G3") else "false")
     if c["kind"] == "a32":
-        return "tsg::tsmm_a32<%d, %d, %d, %d, %d, %s, %d, %d, %d, %s>" % (
-            M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, c.get("FL", 0), "true" if c.get("RB") else "false")
+        return "tsg::tsmm_a32<%d, %d, %d, %d, %d, %s, %d, %d, %d, %s, %s>" % (
+            M, N, c["MS"], c["NB"], c["U"], cplx, c["WPB"], nbuf, c.get("FL", 0), "true" if c.get("RB") else "false",
+            "true" if c.get("G3") else "false")
     if c["kind"] == "lds":
-        return "tsg::tsmttsm_lds<%d, %d, %d, %d, %d, %d, %d, %s, %s, %d, %d>" % (
+        return "tsg::tsmttsm_lds%s<%d, %d, %d, %d, %d, %d, %d, %s, %s, %d, %d>" % (
+            "_a32" if is_a32(v["dt"]) else "",
             M, N, c["MB"], c["NB"], c["WM"], c["WN"], c["RT"], cplx, "true" if c.get("G3") else "false",
             c.get("OCC", 1), c.get("IL", 0))
     if v["op"] == "tsmttsm":

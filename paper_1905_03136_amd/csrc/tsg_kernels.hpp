@@ -1641,8 +1641,13 @@ __device__ __forceinline__ zf lds_elem32(const float* p, int idx, zf) { return z
 // blocks of 16 x 16 per wave, MW waves sharing a row group's rows, U groups of
 // four rows per tile, NBUF register sets in flight, optional slab reads FL),
 // with binary32 products and the binary64 flush every RUN tiles (4 U RUN = 32
-// rows per binary32 sum).  Complex data use four real products per block.
-template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1, int FL = 0>
+// rows per binary32 sum).  Complex data use four real products per block,
+// or with G3 Gauss's three: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi)
+// summed in binary32 over the stretch, then Cr += P1 - P2 and
+// Ci += P3 - P1 - P2 formed in binary64 at the flush (so the binary64 sums
+// stay two per block).
+template <int MC, int NC, int MB, int NB, int MW, int U, bool CPLX, int WPB, int NBUF, int OCC = 1, int FL = 0,
+          bool G3 = false>
 __global__ void __launch_bounds__(WPB * kWave, OCC)
 tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
             const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
@@ -1656,6 +1661,7 @@ tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int RUN = 8 / U;  // tiles per binary32 stretch: 4 U RUN = 32 rows
     constexpr int EMAX = (MC ? MC : MW * MB * 16) * (NC ? NC : NB * 16) * CW;
     static_assert(WPB % MW == 0 && 8 % U == 0, "waves split evenly; U divides 8");
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
     static_assert(FL == 0 || (MW == 1 && MC > 0 && NC > 0 && (MC * CW) % FL == 0 && (NC * CW) % FL == 0),
                   "slab reads: compile-time widths whose rows are multiples of FL, one wave per row group");
     __shared__ double part[EMAX];
@@ -1689,8 +1695,9 @@ tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
 
     dbl4 acc[MB][NB];                     // binary64 sums of the stretches
     dbl4 acci[CPLX ? MB : 1][CPLX ? NB : 1];
-    flt4 s32[MB][NB];                     // binary32 sums of the current stretch
-    flt4 s32i[CPLX ? MB : 1][CPLX ? NB : 1];
+    flt4 s32[MB][NB];                     // binary32 sums of the current stretch (G3: P1)
+    flt4 s32i[CPLX ? MB : 1][CPLX ? NB : 1];  // (G3: P2)
+    flt4 s32s[G3 ? MB : 1][G3 ? NB : 1];      // G3: P3
     const flt4 fz = flt4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -1702,17 +1709,30 @@ tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
                 s32i[i][j] = fz;
             }
+            if constexpr (G3) s32s[i][j] = fz;
         }
     auto flush = [&]() {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                acc[i][j] = widen_add(acc[i][j], s32[i][j]);
-                s32[i][j] = fz;
-                if constexpr (CPLX) {
-                    acci[i][j] = widen_add(acci[i][j], s32i[i][j]);
+                if constexpr (G3) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double p1 = (double)s32[i][j][r], p2 = (double)s32i[i][j][r];
+                        acc[i][j][r] += p1 - p2;
+                        acci[i][j][r] += (double)s32s[i][j][r] - p1 - p2;
+                    }
+                    s32[i][j] = fz;
                     s32i[i][j] = fz;
+                    s32s[i][j] = fz;
+                } else {
+                    acc[i][j] = widen_add(acc[i][j], s32[i][j]);
+                    s32[i][j] = fz;
+                    if constexpr (CPLX) {
+                        acci[i][j] = widen_add(acci[i][j], s32i[i][j]);
+                        s32i[i][j] = fz;
+                    }
                 }
             }
     };
@@ -1783,6 +1803,27 @@ tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
                     for (int j = 0; j < NB; ++j) s32[i][j] = mfma16f(av[u][i], bv[u][j], s32[i][j]);
+            } else if constexpr (G3) {
+                float ai[MB], sa[MB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    ai[i] = conj ? -av[u][i].im : av[u][i].im;
+                    sa[i] = av[u][i].re + ai[i];
+                }
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32[i][j] = mfma16f(av[u][i].re, bv[u][j].re, s32[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32i[i][j] = mfma16f(ai[i], bv[u][j].im, s32i[i][j]);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float sb = bv[u][j].re + bv[u][j].im;
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) s32s[i][j] = mfma16f(sa[i], sb, s32s[i][j]);
+                }
             } else {
                 // Re(a) products of every block first, then Im(a): dependent
                 // updates of one accumulator are 2 MB NB instructions apart
@@ -1837,19 +1878,235 @@ tsmttsm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     block_out<CW>(part, E, N, ws, C, ldc);
 }
 
+// TSMTTSM in binary32 arithmetic with the rows staged in LDS (the scheme of
+// tsmttsm_lds for binary32 storage): stages of RT rows brought by direct
+// 16-byte loads, WM x WN waves of MB x NB blocks, binary32 products summed by
+// the matrix cores over stretches of 32 rows and added into binary64 sums
+// (complex: four products per block, or with G3 Gauss's three, combined in
+// binary64 at each flush as in tsmttsm_a32).  Rows of A and B must hold a
+// multiple of four binary32 values (whole 16-byte loads; lane addresses past
+// the end are clamped to the last 16 bytes, which then hold only values of
+// rows past K, zeroed when read).
+template <int MC, int NC, int MB, int NB, int WM, int WN, int RT, bool CPLX, bool G3 = false, int OCC = 1,
+          int IL = 0>
+__global__ void __launch_bounds__(WM * WN * kWave, OCC)
+tsmttsm_lds_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+                const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
+                double* __restrict__ ws, int conj)
+{
+    using T = elem32_t<CPLX>;
+    constexpr int CW = CPLX ? 2 : 1;
+    constexpr int WPB = WM * WN;
+    constexpr int KS = RT / 4;                                   // 4-row steps of a stage
+    constexpr int FLUSH = 32 / RT;                               // stages per binary32 stretch
+    static_assert(MC > 0 && NC > 0 && (RT == 16 || RT == 32), "compile-time widths; stages of 16 or 32 rows");
+    static_assert(WM * MB * 16 >= MC && WN * NB * 16 >= NC, "the waves' blocks cover C");
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
+    static_assert((MC * CW) % 4 == 0 && (NC * CW) % 4 == 0, "rows of whole 16-byte loads");
+    constexpr int SA = ((RT * MC * CW + 255) / 256) * 256;       // floats of A per stage (whole 1 KB loads)
+    constexpr int SB = ((RT * NC * CW + 255) / 256) * 256;
+    constexpr int SS = SA + SB;                                   // one stage
+    constexpr int E = MC * NC * CW;                               // doubles of the partial
+    constexpr int LDSF = 2 * SS > 2 * E ? 2 * SS : 2 * E;         // floats: two stages, or the partial
+    constexpr int NLA = SA / 256, NLB = SB / 256;                 // wave loads per stage
+    __shared__ __attribute__((aligned(16))) float lds[LDSF];
+
+    const float* __restrict__ A = static_cast<const float*>(Av);
+    const float* __restrict__ B = static_cast<const float*>(Bv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wm = wave % WM, wn = wave / WM;
+    const int lr = lane >> 4;
+    const int lc = lane & 15;
+    const int64_t totA = K * (int64_t)(MC * CW), totB = K * (int64_t)(NC * CW);   // floats
+    const int64_t lastA = totA - 4, lastB = totB - 4;
+
+    auto stage = [&](int64_t t, int b) {
+        float* dst = lds + b * SS;
+        const int64_t ea = t * (int64_t)(RT * MC * CW), eb = t * (int64_t)(RT * NC * CW);
+#pragma unroll
+        for (int i = wave; i < NLA + NLB; i += WPB) {
+            if (i < NLA) {
+                const int64_t e = ea + (int64_t)i * 256 + 4 * lane;
+                __builtin_amdgcn_global_load_lds(A + (e <= lastA ? e : lastA), dst + i * 256, 16, 0, 0);
+            } else {
+                const int64_t e = eb + (int64_t)(i - NLA) * 256 + 4 * lane;
+                __builtin_amdgcn_global_load_lds(B + (e <= lastB ? e : lastB), dst + SA + (i - NLA) * 256, 16, 0, 0);
+            }
+        }
+    };
+
+    int moff[MB], noff[NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int m = (wm * MB + i) * 16 + lc;
+        moff[i] = m < MC ? m : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int n = (wn * NB + j) * 16 + lc;
+        noff[j] = n < NC ? n : 0;
+    }
+
+    dbl4 acc[MB][NB];
+    dbl4 acci[CPLX ? MB : 1][CPLX ? NB : 1];
+    flt4 s32[MB][NB];                          // binary32 stretch sums (G3: P1)
+    flt4 s32i[CPLX ? MB : 1][CPLX ? NB : 1];   // (G3: P2)
+    flt4 s32s[G3 ? MB : 1][G3 ? NB : 1];       // G3: P3
+    const flt4 fz = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+            s32[i][j] = fz;
+            if constexpr (CPLX) {
+                acci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+                s32i[i][j] = fz;
+            }
+            if constexpr (G3) s32s[i][j] = fz;
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if constexpr (G3) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double p1 = (double)s32[i][j][r], p2 = (double)s32i[i][j][r];
+                        acc[i][j][r] += p1 - p2;
+                        acci[i][j][r] += (double)s32s[i][j][r] - p1 - p2;
+                    }
+                    s32s[i][j] = fz;
+                } else {
+                    acc[i][j] = widen_add(acc[i][j], s32[i][j]);
+                    if constexpr (CPLX) acci[i][j] = widen_add(acci[i][j], s32i[i][j]);
+                }
+                s32[i][j] = fz;
+                if constexpr (CPLX) s32i[i][j] = fz;
+            }
+    };
+
+    const int64_t ntiles = (K + RT - 1) / RT;
+    const int64_t G = gridDim.x;
+    int64_t t = blockIdx.x;
+    int stretch = 0;
+    if (t < ntiles) stage(t, 0);
+    for (int b = 0; t < ntiles; t += G, b ^= 1) {
+        __syncthreads();
+        const float* sa = lds + b * SS;
+        const float* sb = sa + SA;
+        T av[KS][MB], bv[KS][NB];
+        auto operands = [&](int s) {
+            const bool ok = t * RT + 4 * s + lr < K;
+            const int r = 4 * s + lr;
+#pragma unroll
+            for (int i = 0; i < MB; ++i) av[s][i] = keep(ok, lds_elem32(sa, r * MC + moff[i], T{}));
+#pragma unroll
+            for (int j = 0; j < NB; ++j) bv[s][j] = keep(ok, lds_elem32(sb, r * NC + noff[j], T{}));
+        };
+#pragma unroll
+        for (int s = 0; s < (IL ? (IL < KS ? IL : KS) : KS); ++s) operands(s);
+        if (t + G < ntiles) stage(t + G, b ^ 1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if constexpr (IL > 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (s + IL < KS) operands(s + IL);
+            }
+            if constexpr (!CPLX) {
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32[i][j] = mfma16f(av[s][i], bv[s][j], s32[i][j]);
+            } else if constexpr (G3) {
+                float ai[MB], sum[MB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    ai[i] = conj ? -av[s][i].im : av[s][i].im;
+                    sum[i] = av[s][i].re + ai[i];
+                }
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32[i][j] = mfma16f(av[s][i].re, bv[s][j].re, s32[i][j]);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) s32i[i][j] = mfma16f(ai[i], bv[s][j].im, s32i[i][j]);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float sbj = bv[s][j].re + bv[s][j].im;
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) s32s[i][j] = mfma16f(sum[i], sbj, s32s[i][j]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        s32[i][j] = mfma16f(av[s][i].re, bv[s][j].re, s32[i][j]);
+                        s32i[i][j] = mfma16f(av[s][i].re, bv[s][j].im, s32i[i][j]);
+                    }
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    const float ai = conj ? -av[s][i].im : av[s][i].im;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        s32[i][j] = mfma16f(ai, -bv[s][j].im, s32[i][j]);
+                        s32i[i][j] = mfma16f(ai, bv[s][j].re, s32i[i][j]);
+                    }
+                }
+            }
+        }
+        if (++stretch == FLUSH) {
+            flush();
+            stretch = 0;
+        }
+    }
+    flush();
+    // the waves own disjoint blocks of C: the block partial is written
+    // directly (into the stage buffers, free once every wave is here)
+    __syncthreads();
+    double* part = reinterpret_cast<double*>(lds);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = (wm * MB + i) * 16 + 4 * lr + r;
+                const int n = (wn * NB + j) * 16 + lc;
+                if (m < MC && n < NC) {
+                    const int e = (m * NC + n) * CW;
+                    part[e] = acc[i][j][r];
+                    if constexpr (CPLX) part[e + 1] = acci[i][j][r];
+                }
+            }
+    __syncthreads();
+    block_out<CW>(part, E, NC, ws, C, ldc);
+}
+
 // TSMM in binary32 arithmetic: the mapping of tsmm_mfma (sixteen rows per
 // product chain, contraction over M in 4-wide slices, C staged once per block
 // in LDS in fragment order, U row blocks per tile), with C rounded to binary32
 // when it is staged and binary32 products summed by the matrix cores (at most
 // 64 products per output).  alpha, beta and the old B are applied in
-// binary64 and the result rounded once to binary32 when it is stored.
-template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, int FL = 0, bool RB = false>
+// binary64 and the result rounded once to binary32 when it is stored.  G3
+// (complex): Gauss's three products P1 = Ar Cr, P2 = Ai Ci,
+// P3 = (Ar + Ai)(Cr + Ci) summed in binary32, Br = P1 - P2 and
+// Bi = P3 - P1 - P2 formed in binary64 (Cr + Ci staged in binary32 beside Cr
+// and Ci).
+template <int MC, int NC, int MS, int NB, int U, bool CPLX, int WPB, int NBUF, int FL = 0, bool RB = false,
+          bool G3 = false>
 __global__ void __launch_bounds__(WPB * kWave)
 tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
          const double* __restrict__ Cm, int64_t ldc, void* __restrict__ Bv, int64_t ldb,
          double alpha, double beta, int conj, int opc)
 {
     static_assert(FL == 0 || (!CPLX && MC > 0 && MC % FL == 0), "slab reads: real data, M a multiple of FL");
+    static_assert(CPLX || !G3, "the three-product form is for complex data");
     using T = elem32_t<CPLX>;
     using S = T;
     constexpr int CW = CPLX ? 2 : 1;
@@ -1858,7 +2115,7 @@ tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int SLAB = FL ? 16 * U * MC : 0;
     constexpr int NL = FL ? (SLAB + kWave * FL - 1) / (kWave * FL) : 1;
     using SV = typename slab_vec<float, FL ? FL : 1>::type;
-    __shared__ float cf[NFRAG * CW];
+    __shared__ float cf[NFRAG * (G3 ? 3 : CW)];
     __shared__ __attribute__((aligned(16))) float slab[FL ? WPB * SLAB : 1];
 
     const S* __restrict__ A = static_cast<const S*>(Av);
@@ -1881,8 +2138,11 @@ tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         const bool ok = m < M && n < N;
         if constexpr (CPLX) {
             const int64_t ci = small_index(m, n, ldc, opc);
-            cf[idx] = ok ? (float)Cm[2 * ci] : 0.0f;
-            cf[NFRAG + idx] = ok ? (float)(opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0f;
+            const double re = ok ? Cm[2 * ci] : 0.0;
+            const double im = ok ? (opc == 2 ? -Cm[2 * ci + 1] : Cm[2 * ci + 1]) : 0.0;
+            cf[idx] = (float)re;
+            cf[NFRAG + idx] = (float)im;
+            if constexpr (G3) cf[2 * NFRAG + idx] = (float)(re + im);
         } else {
             cf[idx] = ok ? (float)Cm[small_index(m, n, ldc, opc)] : 0.0f;
         }
@@ -1950,12 +2210,14 @@ tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
         }
         flt4 acc[U][NB];
         flt4 acci[CPLX ? U : 1][CPLX ? NB : 1];
+        flt4 accs[G3 ? U : 1][G3 ? NB : 1];  // G3: P1 in acc, P2 in acci, P3 in accs
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 acc[u][j] = flt4{0.f, 0.f, 0.f, 0.f};
                 if constexpr (CPLX) acci[u][j] = flt4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (G3) accs[u][j] = flt4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
         for (int s = 0; s < MS; ++s) {
@@ -1965,6 +2227,31 @@ tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                     const float cr = cf[(s * NB + j) * kWave + lane];
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u][j] = mfma16f(av[u][s], cr, acc[u][j]);
+                }
+            } else if constexpr (G3) {
+                float ai[U], sa[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    ai[u] = conj ? -av[u][s].im : av[u][s].im;
+                    sa[u] = av[u][s].re + ai[u];
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float cr = cf[(s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc[u][j] = mfma16f(av[u][s].re, cr, acc[u][j]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float ci = cf[NFRAG + (s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acci[u][j] = mfma16f(ai[u], ci, acci[u][j]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const float cs = cf[2 * NFRAG + (s * NB + j) * kWave + lane];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) accs[u][j] = mfma16f(sa[u], cs, accs[u][j]);
                 }
             } else {
                 float cr[NB], ci[NB];
@@ -2014,7 +2301,13 @@ tsmm_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                                     v = __builtin_fma(beta, ld_plain(p), v);
                                 st_out<kStream>(p, v);
                             } else {
-                                zd v = zd{alpha * (double)acc[u][j][r], alpha * (double)acci[u][j][r]};
+                                double br = (double)acc[u][j][r], bi = (double)acci[u][j][r];
+                                if constexpr (G3) {
+                                    const double p1 = br, p2 = bi;
+                                    br = p1 - p2;
+                                    bi = (double)accs[u][j][r] - p1 - p2;
+                                }
+                                zd v = zd{alpha * br, alpha * bi};
                                 if (RB || read_b) {
                                     zd o;
                                     if constexpr (RB)

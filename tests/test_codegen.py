@@ -59,17 +59,20 @@ def test_default_configs_respect_register_budget():
 
 
 def test_binary32_arithmetic_candidates_and_defaults():
-    """r32a / c64a: their own binary32-product kernels plus every candidate of
-    the binary64-arithmetic twin; the tuning library holds only their own."""
+    """r32a / c64a: their own binary32-product kernels (register rings, and
+    for TSMTTSM the LDS-staged kernel) plus every candidate of the
+    binary64-arithmetic twin (which has no LDS-staged kernel for binary32
+    storage); the tuning library holds only their own."""
     for op in codegen.OPS:
         for dt, twin in codegen.A32_TWIN.items():
             for M, N in ((32, 32), (64, 64), (8, 32)):
                 c = codegen.candidates(op, dt, M, N)
-                own = [x for x in c if x["kind"] == "a32"]
+                own = [x for x in c if x["kind"] in ("a32", "lds")]
                 assert own and len(c) == len(own) + len(codegen.candidates(op, twin, M, N))
+                assert any(x["kind"] == "lds" for x in own) == (op == "tsmttsm" and max(M, N) > 16)
                 assert codegen.default_config(op, dt, M, N)["kind"] == "a32"
     tv = codegen.tuning_variants([(32, 32)])
-    assert all(x["cfg"]["kind"] == "a32" for x in tv if x["M"] and codegen.is_a32(x["dt"]))
+    assert all(x["cfg"]["kind"] in ("a32", "lds") for x in tv if x["M"] and codegen.is_a32(x["dt"]))
     names = {codegen.variant_name(x) for x in tv}
     assert "tsmttsm_r32a_32x32_a32_b2x2w1_u2" in names
 
