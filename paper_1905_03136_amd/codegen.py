@@ -122,8 +122,7 @@ def _lds_candidates(op, dt, M, N):
                 if acc > 64:
                     continue
                 for rt in (16, 32, 64):
-                    stage = 2 * (_ceil(rt * M * cw, 128) + _ceil(rt * N * cw, 128)) * 128 * 8
-                    lds = max(stage, M * N * cw * 8)
+                    lds = 2 * (_ceil(rt * M * cw, 128) + _ceil(rt * N * cw, 128)) * 128 * 8
                     if lds > LDS_BYTES:
                         continue
                     # IL: operand reads of a stage all at once (0) or IL steps
@@ -180,8 +179,7 @@ def _lds32_candidates(op, dt, M, N):
                 if acc > 80:
                     continue
                 for rt in (16, 32):
-                    stage = 2 * (_ceil(rt * M * cw, 256) + _ceil(rt * N * cw, 256)) * 256 * 4
-                    lds = max(stage, M * N * cw * 8)
+                    lds = 2 * (_ceil(rt * M * cw, 256) + _ceil(rt * N * cw, 256)) * 256 * 4
                     if lds > LDS_BYTES:
                         continue
                     for il in (0, 1, 2):

@@ -563,6 +563,35 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // element would share its 16 bytes with the end and be moved by the clamp.)
 // ============================================================================
 
+// Epilogue of the LDS-staged kernels, whose waves own disjoint blocks of C:
+// lane (lr, lc) holds entry r of block (i, j) at row 16 (wm MB + i) + lr + 4 r
+// (binary64 products) or + 4 lr + r (binary32 products, f32rows), column
+// 16 (wn NB + j) + lc.  Each entry is written once, to slot blockIdx.x of the
+// workspace in block_out's layout (E doubles per slot) or, for a grid of one
+// block, to C.
+template <int CW, int MB, int NB, class ACC, class ACCI>
+__device__ __forceinline__ void lds_out(const ACC& acc, const ACCI& acci, int wm, int wn, int lr, int lc, int MC,
+                                        int NC, int E, double* __restrict__ ws, double* __restrict__ C, int64_t ldc,
+                                        bool f32rows)
+{
+    const bool direct = gridDim.x == 1;
+    double* dst = ws + (direct ? 0 : (size_t)blockIdx.x * E);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = (wm * MB + i) * 16 + (f32rows ? 4 * lr + r : lr + 4 * r);
+                const int n = (wn * NB + j) * 16 + lc;
+                if (m < MC && n < NC) {
+                    double* p = direct ? C + ((int64_t)m * ldc + n) * CW : dst + (m * NC + n) * CW;
+                    p[0] = acc[i][j][r];
+                    if constexpr (CW == 2) p[1] = acci[i][j][r];
+                }
+            }
+}
+
 // One wave-wide direct load: 64 lanes x 16 bytes from src + 2 lane (doubles)
 // into 1 KB of LDS at dst (the hardware places lane l at dst + 16 l).
 __device__ __forceinline__ void dma16(const double* src, double* dst)
@@ -589,9 +618,8 @@ tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
     constexpr int SB = ((RT * NC * CW + 127) / 128) * 128;
     constexpr int SS = SA + SB;                                   // one stage
     constexpr int E = MC * NC * CW;
-    constexpr int LDSN = 2 * SS > E ? 2 * SS : E;                 // two stages; the partial reuses them
     constexpr int NLA = SA / 128, NLB = SB / 128;                 // wave loads per stage
-    __shared__ __attribute__((aligned(16))) double lds[LDSN];
+    __shared__ __attribute__((aligned(16))) double lds[2 * SS];  // two stages
 
     const double* __restrict__ A = static_cast<const double*>(Av);
     const double* __restrict__ B = static_cast<const double*>(Bv);
@@ -734,26 +762,10 @@ tsmttsm_lds(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
                 acci[i][j] = accs[i][j] - p1 - p2;
             }
     }
-    // the waves own disjoint blocks of C: the block partial is written
-    // directly (into the stage buffers, free once every wave is here)
-    __syncthreads();
-    double* part = lds;
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = (wm * MB + i) * 16 + lr + 4 * r;
-                const int n = (wn * NB + j) * 16 + lc;
-                if (m < MC && n < NC) {
-                    const int e = (m * NC + n) * CW;
-                    part[e] = acc[i][j][r];
-                    if constexpr (CPLX) part[e + 1] = acci[i][j][r];
-                }
-            }
-    __syncthreads();
-    block_out<CW>(part, E, NC, ws, C, ldc);
+    // the waves own disjoint blocks of C: every lane writes its entries of
+    // the block partial (slot blockIdx.x of the workspace, as block_out
+    // lays it out) or, for a grid of one block, of C itself
+    lds_out<CW, MB, NB>(acc, acci, wm, wn, lr, lc, MC, NC, E, ws, C, ldc, false);
 }
 
 // ============================================================================
@@ -1907,9 +1919,8 @@ tsmttsm_lds_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t 
     constexpr int SB = ((RT * NC * CW + 255) / 256) * 256;
     constexpr int SS = SA + SB;                                   // one stage
     constexpr int E = MC * NC * CW;                               // doubles of the partial
-    constexpr int LDSF = 2 * SS > 2 * E ? 2 * SS : 2 * E;         // floats: two stages, or the partial
     constexpr int NLA = SA / 256, NLB = SB / 256;                 // wave loads per stage
-    __shared__ __attribute__((aligned(16))) float lds[LDSF];
+    __shared__ __attribute__((aligned(16))) float lds[2 * SS];   // two stages
 
     const float* __restrict__ A = static_cast<const float*>(Av);
     const float* __restrict__ B = static_cast<const float*>(Bv);
@@ -2066,26 +2077,8 @@ tsmttsm_lds_a32(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t 
         }
     }
     flush();
-    // the waves own disjoint blocks of C: the block partial is written
-    // directly (into the stage buffers, free once every wave is here)
-    __syncthreads();
-    double* part = reinterpret_cast<double*>(lds);
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = (wm * MB + i) * 16 + 4 * lr + r;
-                const int n = (wn * NB + j) * 16 + lc;
-                if (m < MC && n < NC) {
-                    const int e = (m * NC + n) * CW;
-                    part[e] = acc[i][j][r];
-                    if constexpr (CPLX) part[e + 1] = acci[i][j][r];
-                }
-            }
-    __syncthreads();
-    block_out<CW>(part, E, NC, ws, C, ldc);
+    // binary32 matrix-core output layout: lane l holds rows 4 (l/16) + r
+    lds_out<CW, MB, NB>(acc, acci, wm, wn, lr, lc, MC, NC, E, ws, C, ldc, true);
 }
 
 // TSMM in binary32 arithmetic: the mapping of tsmm_mfma (sixteen rows per
