@@ -33,6 +33,10 @@ OPS = {"tsmttsm": 0, "tsmm": 1}
 # widths of the plain sweep and the square widths of the target range
 GRADED = [(1, 1), (2, 2), (4, 4), (8, 8), (16, 16), (32, 32), (64, 64), (32, 8), (8, 32)]
 SQUARE_ALL = [(w, w) for w in range(1, 65)]
+# narrow non-square pairs (block vectors of up to eight columns against one
+# another): exact-width kernels too, since the run-time-width kernels pad
+# them to whole 4-wide slices or 16-column blocks
+NARROW = [(m, n) for m in range(1, 9) for n in range(1, 9) if m != n]
 # pre-generated widths of the precision form (others use run-time-width variants)
 PRECISION = GRADED
 # widths whose every candidate the default build compiles into the tuning
@@ -948,7 +952,7 @@ def _write_if_changed(path, text):
 
 
 def all_variants(widths=None, tuned_path=None):
-    widths = (GRADED + SQUARE_ALL) if widths is None else widths
+    widths = (GRADED + SQUARE_ALL + NARROW) if widths is None else widths
     seen = set()
     uniq = []
     for (M, N) in widths:

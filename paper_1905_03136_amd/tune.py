@@ -41,6 +41,8 @@ def _widths(name):
         return codegen.GRADED
     if name == "square":
         return codegen.SQUARE_ALL
+    if name == "narrow":
+        return codegen.NARROW
     out = []
     for tok in name.split(","):
         m, n = tok.split("x")

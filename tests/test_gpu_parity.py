@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1905_03136_amd import _lib, api, inputs
+from paper_1905_03136_amd import _lib, api, codegen, inputs
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -100,16 +100,33 @@ def test_integer_inputs_bit_exact(M, N, cplx):
 def test_every_square_width(w, cplx):
     """Each square width runs its own (tuned or default) variant: both products
     against the compensated oracle, integer inputs bit for bit."""
+    check_width(w, w, cplx)
+
+
+@pytest.mark.parametrize("M,N", codegen.NARROW)
+@pytest.mark.parametrize("cplx", [False, True])
+def test_every_narrow_pair(M, N, cplx):
+    """The narrow non-square pairs (up to 8 x 8) run exact-width variants of
+    their own, checked like the square widths."""
+    dt = "c128" if cplx else "r64"
+    for op in ("tsmttsm", "tsmm"):
+        name = api.kernel_name(op, torch.complex128 if cplx else torch.float64, M, N)
+        assert name.startswith("%s_%s_%dx%d_" % (op, dt, M, N)), name
+    check_width(M, N, cplx)
+
+
+def check_width(M, N, cplx):
     K = 20011                                       # several tiles and a ragged tail
-    A = inputs.host_uniform(K, w, 23, inputs.STREAM_A, cplx)
-    B = inputs.host_uniform(K, w, 23, inputs.STREAM_B, cplx)
-    X = inputs.host_uniform(w, w, 23, inputs.STREAM_C, cplx)
+    print("width %dx%d %s" % (M, N, "Z" if cplx else "D"), flush=True)
+    A = inputs.host_uniform(K, M, 23, inputs.STREAM_A, cplx)
+    B = inputs.host_uniform(K, N, 23, inputs.STREAM_B, cplx)
+    X = inputs.host_uniform(M, N, 23, inputs.STREAM_C, cplx)
     dA, dB, dX = dev(A), dev(B), dev(X)
     check_close(host(api.tsmttsm(dA, dB)), oracle.tsmttsm(A, B, compensated=True), abs_bound_tsmttsm(A, B, "T"))
     check_close(host(api.tsmm(dA, dX)), oracle.tsmm(A, X, compensated=True), np.abs(A) @ np.abs(X))
-    Ai = inputs.host_integers(K, w, 24, inputs.STREAM_A, cplx)
-    Bi = inputs.host_integers(K, w, 24, inputs.STREAM_B, cplx)
-    Xi = inputs.host_integers(w, w, 24, inputs.STREAM_C, cplx)
+    Ai = inputs.host_integers(K, M, 24, inputs.STREAM_A, cplx)
+    Bi = inputs.host_integers(K, N, 24, inputs.STREAM_B, cplx)
+    Xi = inputs.host_integers(M, N, 24, inputs.STREAM_C, cplx)
     Ci, Pi = oracle.tsmttsm(Ai, Bi), oracle.tsmm(Ai, Xi)
     Ui = oracle.tsmm(Ai, Xi, Bi.copy(), alpha=-1.0, beta=1.0)    # update form B - A C
 
