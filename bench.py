@@ -375,11 +375,44 @@ def small_k_leg(torch, api, inputs, dev, K=1 << 20, M=4, N=4, sets=20, reps=5):
     ts.sort()
     t = ts[len(ts) // 2]
     byts, flops = algorithmic("tsmttsm", False, K, M, N)
-    del pairs
+    # The same calls captured in one hipGraph and replayed (a launch-bound
+    # loop's deployment): per-call device time without the host's time to
+    # issue each call, which the eager figure above includes whenever the
+    # host is slower than the kernels.  Each replay is checked against the
+    # eager results.
+    cs = torch.cuda.Stream()
+    Cs = [torch.empty((M, N), dtype=torch.float64, device=dev) for _ in pairs]
+    with torch.cuda.stream(cs):
+        for (a, b), c in zip(pairs, Cs):
+            api.tsmttsm(a, b, out=c)      # sizes the capture stream's workspace
+    cs.synchronize()
+    eager = [c.clone() for c in Cs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        for (a, b), c in zip(pairs, Cs):
+            api.tsmttsm(a, b, out=c)
+    tg = []
+    for _ in range(reps):
+        for c in Cs:
+            c.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        tg.append(e0.elapsed_time(e1) * 1e-3 / len(pairs))
+        assert all(torch.equal(c, e) for c, e in zip(Cs, eager)), "graph replay differs from the eager calls"
+    tg.sort()
+    t_graph = tg[len(tg) // 2]
+    del pairs, g
     return {"workload": "TSMTTSM D K=2^20 M=N=4, %d operand sets rotated (%.2f GB)" % (sets, sets * 8 * K * (M + N) / 1e9),
             "us": round(t * 1e6, 2), "us_min": round(ts[0] * 1e6, 2), "us_max": round(ts[-1] * 1e6, 2),
             "GBps": round(byts / t / 1e9, 1), "roof_frac": round(roofline_time(byts, flops) / t, 4),
-            "kernel": api.kernel_name("tsmttsm", torch.float64, M, N), "calls_timed": len(ts)}
+            "us_graph": round(t_graph * 1e6, 2), "GBps_graph": round(byts / t_graph / 1e9, 1),
+            "roof_frac_graph": round(roofline_time(byts, flops) / t_graph, 4),
+            "kernel": api.kernel_name("tsmttsm", torch.float64, M, N), "calls_timed": len(ts),
+            "note": "us: eager calls, one event pair each (includes the host's issue time when it exceeds the "
+                    "kernel's); us_graph: the %d calls replayed from one captured graph, per call" % len(Cs)}
 
 
 def autograd_leg(torch, inputs, dev, K=1 << 22, w=32, reps=5):
@@ -406,6 +439,11 @@ def autograd_leg(torch, inputs, dev, K=1 << 22, w=32, reps=5):
         tf = time_stats(torch, fwd, reps=reps, warmup=1)
         fwd()
         tb = time_stats(torch, bwd, reps=reps, warmup=1)
+        # back to back (as a training loop issues them): per-call time of 8
+        # calls between one event pair, the host's issue time overlapped
+        tfp = time_stats(torch, lambda: [fwd() for _ in range(8)], reps=3, warmup=1)["median"] / 8
+        fwd()
+        tbp = time_stats(torch, lambda: [bwd() for _ in range(8)], reps=3, warmup=1)["median"] / 8
         s = 16 if cplx else 8
         fb = s * K * 2 * w + s * w * w
         bb = 2 * s * K * 2 * w + 2 * s * w * w
@@ -414,7 +452,10 @@ def autograd_leg(torch, inputs, dev, K=1 << 22, w=32, reps=5):
                     "forward_us": round(tf["median"] * 1e6, 1), "backward_us": round(tb["median"] * 1e6, 1),
                     "forward_GBps": round(fb / tf["median"] / 1e9, 1), "backward_GBps": round(bb / tb["median"] / 1e9, 1),
                     "forward_roof_frac": round(roofline_time(fb, ff) / tf["median"], 4),
-                    "backward_roof_frac": round(roofline_time(bb, 2 * ff) / tb["median"], 4)})
+                    "backward_roof_frac": round(roofline_time(bb, 2 * ff) / tb["median"], 4),
+                    "forward_us_back_to_back": round(tfp * 1e6, 1), "backward_us_back_to_back": round(tbp * 1e6, 1),
+                    "forward_roof_frac_back_to_back": round(roofline_time(fb, ff) / tfp, 4),
+                    "backward_roof_frac_back_to_back": round(roofline_time(bb, 2 * ff) / tbp, 4)})
         del A, B, dC, holder
         torch.cuda.empty_cache()
     return out
