@@ -148,7 +148,9 @@ def predict(v, K, res=None):
     if v["op"] == "tsmm":
         bw = min(bw, mix_ceiling(M, N))
     fm, fv = executed_flops(v, K)
-    p_mfma = P_MFMA * (2.0 if v["dt"] in ("r32a", "c64a") and v["cfg"]["kind"] == "a32" else 1.0)
+    # binary32 products (the a32 kernels and the LDS-staged kernel of the
+    # binary32-arithmetic types) run at twice the binary64 matrix-core rate
+    p_mfma = P_MFMA * (2.0 if v["dt"] in ("r32a", "c64a") and v["cfg"]["kind"] in ("a32", "lds") else 1.0)
     p_mfma *= MFMA_BY_WAVES.get(waves_per_simd(v, res), 1.0)
     return max(byts / bw, fm / p_mfma, fv / P_VALU) + T_LAUNCH
 
