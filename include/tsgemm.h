@@ -117,10 +117,14 @@ typedef enum {
  * TSG_R32_ACC32 / TSG_C64_ACC32: binary32 products summed in binary32 over
  * stretches of at most 32 rows of a thread, each stretch sum then added in
  * binary64; every entry is within c 2^-24 sum_k |op(a_km)| |b_kn| of the
- * exact sum of the stored values, c = 34 (real) or 66 (each part of a
- * complex entry, which sums two real products per row).  Where binary64
- * arithmetic on the widened values is as fast, the library uses it instead
- * (more accurate, same bound).
+ * exact sum of the stored values (|.| the modulus for complex values),
+ * c = 34 (real) or 66 (each part of a complex entry, which sums two real
+ * products per row).  Complex kernels in Gauss's three-product form (binary32
+ * sums of Ar Br, Ai Bi and (Ar + Ai)(Br + Bi), combined in binary64) give
+ * c = 34 for the real part and c = 106 for the imaginary part, which cancels
+ * where the parts of the data do.  Where binary64 arithmetic on the widened
+ * values is as fast, the library uses it instead (more accurate, within the
+ * same bound).
  */
 tsg_status tsg_tsmttsm(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, int32_t N,
                        const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -169,7 +173,9 @@ tsg_status tsg_tsmttsm_noalloc(tsg_dtype dt, tsg_op op, int64_t K, int32_t M, in
  * TSG_C64_ACC32: C is rounded to binary32 and the sum over m (at most 64
  * products) taken in binary32, alpha and beta B in binary64, the result
  * rounded once to binary32: within (M + 3) 2^-24 sum_m |a_km| |c_mn| plus
- * one binary32 rounding of the result (per real part; complex: 2M + 3).
+ * one binary32 rounding of the result (per real part; complex: 2M + 3, or
+ * with Gauss's three-product form M + 3 for the real part and 3M + 13 for
+ * the imaginary part).
  */
 tsg_status tsg_tsmm(tsg_dtype dt, int32_t conjA, int64_t K, int32_t M, int32_t N,
                     const void *A, int64_t lda, const void *C, int64_t ldc,
