@@ -657,6 +657,26 @@ def pair_table(path):
     return "\n".join(out)
 
 
+def reduction_table(path):
+    """Markdown table of the JSON lines a --reduction-sweep run printed."""
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{"):
+                r = json.loads(line)
+                if "fold" in r:
+                    rows.append(r)
+    out = ["| M = N | K | fold us | fold overhead | atomic us | atomic overhead | none us | fraction (fold) |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| %d | %d | %.1f | %+.0f%% | %.1f | %+.0f%% | %.1f | %.3f |" % (
+            r["M"], r["K"], r["fold"]["us"], 100 * r["fold"]["overhead_vs_none"], r["atomic"]["us"],
+            100 * r["atomic"]["overhead_vs_none"], r["none"]["us"], r["fold"]["roof_frac"]))
+    out.append("\n```json\n%s\n```" % json.dumps(rows))
+    return "\n".join(out)
+
+
 def reduction_sweep(torch, api, inputs, dev, widths=(4, 32), Ks=(10**3, 10**4, 10**5, 10**6, 10**7, 10**8),
                     reps=20):
     """Ablation of TSMTTSM's cross-block reduction against K (the paper's
@@ -724,6 +744,8 @@ def main():
                     help="instead of the bench step: nonsymmetric (M, N) grid, D and Z, both products")
     ap.add_argument("--pair-table", default="",
                     help="no GPU: print the markdown tables of a --pair-sweep run's JSON lines (file) and exit")
+    ap.add_argument("--reduction-table", default="",
+                    help="no GPU: print the markdown table of a --reduction-sweep run's JSON lines (file) and exit")
     ap.add_argument("--reduction-sweep", action="store_true",
                     help="instead of the bench step: TSMTTSM reduction variants (fold / atomic / none) against K")
     ap.add_argument("--vendor", action="store_true",
@@ -731,6 +753,9 @@ def main():
     a = ap.parse_args()
     if a.pair_table:
         print(pair_table(a.pair_table))
+        return
+    if a.reduction_table:
+        print(reduction_table(a.reduction_table))
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "

@@ -37,3 +37,14 @@ def test_probe_markdown_tables():
     assert "| 1:1 streaming | 5384 | 2 | 8 |" in text
     assert "| mfma_f64 | 37.9 | 51.5 |" in text
     assert "| 1 MiB | 298 | 124 |" in text
+
+
+def test_reduction_table_rows(tmp_path):
+    rec = {"M": 4, "N": 4, "K": 1000, "sets": 2, "kernel": "k",
+           "fold": {"us": 12.0, "GBps": 1.0, "roof_frac": 0.0123, "overhead_vs_none": 0.2},
+           "atomic": {"us": 15.0, "GBps": 1.0, "roof_frac": 0.01, "overhead_vs_none": 0.5},
+           "none": {"us": 10.0, "GBps": 1.0, "roof_frac": 0.02}}
+    path = tmp_path / "red.jsonl"
+    path.write_text("x\n" + json.dumps(rec) + "\n")
+    text = bench.reduction_table(str(path))
+    assert "| 4 | 1000 | 12.0 | +20% | 15.0 | +50% | 10.0 | 0.012 |" in text
