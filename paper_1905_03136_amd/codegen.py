@@ -358,6 +358,11 @@ def _candidates(op, dt, M, N):
                 for w in (4, 8):
                     for nbuf in (2, 4):
                         out.append(dict(kind="packed", U=u, WPB=w, NBUF=nbuf))
+        if M == 1 and N == 1 and not cplx and not is_f32(dt):
+            # the dot product: pairs of rows as 16-byte loads (contiguous vectors)
+            for u in (1, 2, 4, 8):
+                for w in (4, 8):
+                    out.append(dict(kind="dot", U=u, WPB=w))
         if M * N * cw <= 64:
             for u in (1, 2, 4):
                 if _valu_regs(op, M, N, cw, u) <= 110:
@@ -723,7 +728,7 @@ def load_tuned(path):
 def needs_layout(cfg):
     """True if a configuration reads A in a way only some layouts allow
     (paired loads, slab reads, direct loads of whole stages into LDS)."""
-    return bool(cfg.get("VA") or cfg.get("FL") or cfg.get("kind") == "lds")
+    return bool(cfg.get("VA") or cfg.get("FL") or cfg.get("kind") in ("lds", "dot"))
 
 
 def exact_variants(widths, tuned=None):
@@ -759,6 +764,8 @@ def variant_name(v):
     w = "%dx%d" % (v["M"], v["N"]) if v["M"] else "le%dx%d" % (v["maxM"], v["maxN"])
     if c["kind"] == "valu":
         tag = "valu_u%d" % c["U"]
+    elif c["kind"] == "dot":
+        tag = "dot_u%d" % c["U"]
     elif c["kind"] == "packed":
         tag = "packed_u%d" % c["U"]
     elif c["kind"] == "a32" and v["op"] == "tsmttsm":
@@ -802,6 +809,8 @@ def _template(v):
     f32 = "true" if is_f32(v["dt"]) else "false"
     if c["kind"] == "packed":
         return "tsg::%s_packed<%d, %d, %d, %s, %d, %d, %s>" % (v["op"], M, N, c["U"], cplx, c["WPB"], nbuf, f32)
+    if c["kind"] == "dot":
+        return "tsg::tsmttsm_dot<%d, %d>" % (c["U"], c["WPB"])
     if c["kind"] == "a32" and v["op"] == "tsmttsm":
         return "tsg::tsmttsm_a32<%d, %d, %d, %d, %d, %d, %s, %d, %d, %d, %d, %s>" % (
             M, N, c["MB"], c["NB"], c["MW"], c["U"], cplx, c["WPB"], nbuf, c.get("OCC", 1), c.get("FL", 0),
@@ -840,6 +849,8 @@ def rows_per_tile(v):
         return (4 if v["op"] == "tsmttsm" else 16) * c["U"] * c["WPB"]
     if c["kind"] == "lds":
         return c["RT"]
+    if c["kind"] == "dot":
+        return 2 * 64 * c["U"] * c["WPB"]
     if v["op"] == "tsmttsm":
         return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 4 * c["U"] * (c["WPB"] // c["MW"])  # mfma, a32
     return 64 * c["U"] * c["WPB"] if c["kind"] == "valu" else 16 * c["U"] * c["WPB"]
@@ -868,9 +879,9 @@ def _record(v, fn):
     pair_x = int((c["kind"] == "valu" and bool(c.get("VB"))) or (v["op"] == "tsmttsm" and slab_pairs))
     even = int(v["M"] == 0 and (pair_a or pair_x))
     pack = 0 if c["kind"] != "packed" else (1 if v["op"] == "tsmttsm" else 2)
-    flat_a = int(bool(c.get("FL")) or c["kind"] == "lds")
+    flat_a = int(bool(c.get("FL")) or c["kind"] in ("lds", "dot"))
     read_b = int(bool(c.get("RB")))
-    align16 = int(c["kind"] == "lds")
+    align16 = int(c["kind"] in ("lds", "dot"))
     return ('    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "%s", &%s, &%s},\n'
             % (OPS[v["op"]], DTYPES[v["dt"]][0], v["M"], v["N"], v["maxM"], v["maxN"], pair_a, pair_x, even,
                64 * c["WPB"], rows_per_tile(v), pack, flat_a, read_b, align16, variant_name(v),

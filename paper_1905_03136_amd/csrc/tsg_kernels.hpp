@@ -1018,6 +1018,74 @@ tsmttsm_valu(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 }
 
 // ============================================================================
+// TSMTTSM for M = N = 1, real: the dot product of two contiguous vectors
+// (lda = ldb = 1, 16-byte aligned).  A lane reads pairs of consecutive rows as
+// one 16-byte load, so every wave load is one 1 KB run of A or B (the
+// per-row kernels above read 512 bytes per wave load); U pairs per lane and
+// matrix in each of the two register sets of the leap frog, two chains of
+// fused multiply-adds per lane.  A pair that reaches past row K - 1 is read
+// as its first element only (the clamped address keeps it inside the
+// matrix) and zero.
+// ============================================================================
+template <int U, int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+tsmttsm_dot(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda,
+            const void* __restrict__ Bv, int64_t ldb, double* __restrict__ C, int64_t ldc,
+            double* __restrict__ ws, int conj)
+{
+    constexpr int RT = 2 * kWave * U * WPB;  // rows per tile
+    __shared__ double part[WPB];
+    const double* __restrict__ A = static_cast<const double*>(Av);
+    const double* __restrict__ B = static_cast<const double*>(Bv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+
+    auto load2 = [&](const double* __restrict__ p, int64_t e) -> dbl2 {
+        if (e + 1 < K) return ld_stream2(p + e);
+        const int64_t c = e < K ? e : K - 1;
+        dbl2 v;
+        v.x = keep(e < K, ld_stream(p + c));
+        v.y = 0.0;
+        return v;
+    };
+    struct Frag {
+        dbl2 a[U];
+        dbl2 b[U];
+    };
+    Frag x, y;
+    double acc0 = 0.0, acc1 = 0.0;
+    auto load = [&](int64_t t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = t * RT + 2 * ((int64_t)(wave * U + u) * kWave + lane);
+            f.a[u] = load2(A, e);
+            f.b[u] = load2(B, e);
+        }
+    };
+    auto compute = [&](int64_t, Frag& f) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc0 = __builtin_fma(f.a[u].x, f.b[u].x, acc0);
+            acc1 = __builtin_fma(f.a[u].y, f.b[u].y, acc1);
+        }
+    };
+    const int64_t ntiles = (K + RT - 1) / RT;
+    leapfrog(blockIdx.x, ntiles, gridDim.x, x, y, load, compute);
+
+    // wave sums (fixed butterfly), then the waves' sums in wave order
+    const double v = wave_sum(acc0 + acc1);
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = part[0];
+        for (int w = 1; w < WPB; ++w) sum += part[w];
+        part[0] = sum;
+    }
+    __syncthreads();
+    block_out<1>(part, 1, 1, ws, C, ldc);
+}
+
+// ============================================================================
 // TSMM on the vector ALUs for narrow widths.
 //
 // Parallelisation over K only (the paper's Fig. "tsmm_mapping_1T" mapping):

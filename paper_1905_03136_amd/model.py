@@ -88,6 +88,8 @@ def rows_ahead(v):
     nbuf = c.get("NBUF", 2)
     if c["kind"] == "lds":
         return c["RT"]
+    if c["kind"] == "dot":
+        return 128 * c["U"] * c["WPB"] * (nbuf - 1)
     if c["kind"] == "packed":
         per = (4 if v["op"] == "tsmttsm" else 16) * c["U"] * c["WPB"]
         P = max(1, 16 // max(v["M"], v["N"])) if v["op"] == "tsmttsm" else max(1, 16 // v["N"])
