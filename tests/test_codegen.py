@@ -162,3 +162,37 @@ def test_product_runtime_width_variants_fit_their_kernels():
         if g["cfg"]["kind"] == "mfma":
             cm, cn = codegen.generic_capacity(g["op"], g["cfg"])
             assert g["maxM"] <= cm and g["maxN"] <= cn, codegen.variant_name(g)
+
+
+def test_layout_restricted_kernels_have_a_fallback_and_flags():
+    """Kernels that need contiguous rows or 16-byte alignment (slab reads,
+    LDS staging, the dot product) carry those flags in their registry record
+    and are followed by a kernel without the need: of the same width, or a
+    run-time-width one covering it (the shipped table's choices)."""
+    import os
+    v = codegen.all_variants(None, os.path.join(os.path.dirname(codegen.__file__), "tuned.json"))
+    by, gens = {}, []
+    for x in v:
+        if x["M"]:
+            by.setdefault((x["op"], x["dt"], x["M"], x["N"]), []).append(x)
+        elif not codegen.needs_layout(x["cfg"]) and not x["cfg"].get("RB"):
+            gens.append(x)
+
+    def generic_covers(op, dt, M, N):
+        dt = codegen.A32_TWIN.get(dt, dt)
+        return any(g["op"] == op and g["dt"] == dt and M <= g["maxM"] and N <= g["maxN"] for g in gens)
+    seen = set()
+    for key, xs in by.items():
+        for i, x in enumerate(xs):
+            c = x["cfg"]
+            if not codegen.needs_layout(c):
+                continue
+            seen.add(c["kind"])
+            rec = codegen._record(x, "launch_x")
+            fields = [f.strip() for f in rec.split("{")[1].split("}")[0].split(",")]
+            flat_a, align16 = int(fields[12]), int(fields[14])
+            if c["kind"] in ("lds", "dot"):
+                assert flat_a == 1 and align16 == 1, codegen.variant_name(x)
+            assert (any(not codegen.needs_layout(y["cfg"]) and not y["cfg"].get("RB") for y in xs[i + 1:])
+                    or generic_covers(*key)), codegen.variant_name(x)
+    assert {"lds", "dot"} <= seen
