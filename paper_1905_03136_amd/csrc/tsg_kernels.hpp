@@ -551,9 +551,12 @@ tsmttsm_mfma(int64_t K, int Mr, int Nr, const void* __restrict__ Av, int64_t lda
 // Each wave reads the operands of its own blocks of C for the whole stage
 // into registers (the matrix-core operand layout of tsmttsm_mfma) right after
 // the barrier that publishes the stage, then issues the loads of the next
-// stage into the other buffer and multiplies.  A block of WM x WN waves
-// covers C with MB x NB blocks of 16 x 16 per wave; every wave reads every
-// row of the stage, each element of A and B crosses HBM once.
+// stage into the other buffer and multiplies (with IL > 0 only the first IL
+// steps are read up front, the rest IL steps ahead of their products).  A
+// block of WM x WN waves covers C with MB x NB blocks of 16 x 16 per wave;
+// every wave reads every row of the stage, each element of A and B crosses
+// HBM once, and each lane writes its entries of the block partial straight
+// from its accumulators (lds_out).
 //
 // Needs lda = M and ldb = N (a stage is one contiguous run of A and one of
 // B), 16-byte aligned A and B, and an even number of doubles in each of A
