@@ -677,6 +677,32 @@ def pair_table(path):
     return "\n".join(out)
 
 
+def vendor_table(path):
+    """Markdown table of the JSON lines an --all-widths --vendor run printed."""
+    rows, summary = [], None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line.startswith("{"):
+                continue
+            r = json.loads(line)
+            if "all_widths_summary" in r:
+                summary = r
+            elif "vendor_us" in r.get("tsmttsm", {}):
+                rows.append(r)
+    out = ["| dtype | w | TSMTTSM ours us | vendor us | ours / vendor speedup | TSMM ours us | vendor us | speedup "
+           "| ours frac (T / M) | vendor frac (T / M) |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---|---|"]
+    for r in rows:
+        t, m = r["tsmttsm"], r["tsmm"]
+        out.append("| %s | %d | %.1f | %.1f | %.0f | %.1f | %.1f | %.2f | %.3f / %.3f | %.4f / %.3f |" % (
+            r["dtype"], r["M"], t["us"], t["vendor_us"], t["speedup_vs_vendor"], m["us"], m["vendor_us"],
+            m["speedup_vs_vendor"], t["roof_frac"], m["roof_frac"], t["vendor_roof_frac"], m["vendor_roof_frac"]))
+    if summary:
+        out.append("\nSummary over these widths:\n\n```json\n%s\n```" % json.dumps(summary, indent=1))
+    return "\n".join(out)
+
+
 def reduction_table(path):
     """Markdown table of the JSON lines a --reduction-sweep run printed."""
     rows = []
@@ -764,6 +790,8 @@ def main():
                     help="instead of the bench step: nonsymmetric (M, N) grid, D and Z, both products")
     ap.add_argument("--pair-table", default="",
                     help="no GPU: print the markdown tables of a --pair-sweep run's JSON lines (file) and exit")
+    ap.add_argument("--vendor-table", default="",
+                    help="no GPU: print the markdown table of an --all-widths --vendor run's JSON lines (file) and exit")
     ap.add_argument("--reduction-table", default="",
                     help="no GPU: print the markdown table of a --reduction-sweep run's JSON lines (file) and exit")
     ap.add_argument("--reduction-sweep", action="store_true",
@@ -776,6 +804,9 @@ def main():
         return
     if a.reduction_table:
         print(reduction_table(a.reduction_table))
+        return
+    if a.vendor_table:
+        print(vendor_table(a.vendor_table))
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the products run on a single MI355X "

@@ -48,3 +48,16 @@ def test_reduction_table_rows(tmp_path):
     path.write_text("x\n" + json.dumps(rec) + "\n")
     text = bench.reduction_table(str(path))
     assert "| 4 | 1000 | 12.0 | +20% | 15.0 | +50% | 10.0 | 0.012 |" in text
+
+
+def test_vendor_table_rows(tmp_path):
+    rec = {"dtype": "D", "M": 8, "N": 8, "K": 16,
+           "tsmttsm": {"us": 10.0, "roof_frac": 0.8, "kernel": "k", "vendor_us": 1000.0, "vendor_roof_frac": 0.008,
+                       "speedup_vs_vendor": 100.0},
+           "tsmm": {"us": 20.0, "roof_frac": 0.6, "kernel": "k", "vendor_us": 40.0, "vendor_roof_frac": 0.3,
+                    "speedup_vs_vendor": 2.0}}
+    path = tmp_path / "v.jsonl"
+    path.write_text(json.dumps(rec) + "\n" + json.dumps({"all_widths_summary": {"D_tsmttsm": {"mean": 0.8}}}) + "\n")
+    text = bench.vendor_table(str(path))
+    assert "| D | 8 | 10.0 | 1000.0 | 100 | 20.0 | 40.0 | 2.00 | 0.800 / 0.600 | 0.0080 / 0.300 |" in text
+    assert "all_widths_summary" in text
